@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the PIC hot path on one MI355X: particle pushes per second.
+
+One step is the full leap-frog cycle (fused gather + Boris push + deposit per
+tile, Yee updates of b and e, periodic counting-sort repacks) over the thermal
+pair plasma workload: 64^3 cells, 64 pairs per cell (33.5 M particles),
+theta = 0.1, dt = 0.5, n_x = 10, uniform density, synthetic seeded inputs that
+stand in for the paper's thermal test problems.
+
+Prints ONE JSON line.  Besides the headline value it carries:
+  roofline      the push kernel's algorithmic HBM bytes per launch divided by
+                its average launch time (HIP events on the library's stream
+                around each launch, over the timed steps), against 8 TB/s;
+                traffic is the counter-measured HBM bytes per launch
+                (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy) when the
+                committed counter summary matches the current kernel source;
+  cpu_baseline  the FP64 CPU oracle timed on a bounded sample of the same
+                workload on this host;
+  fp64_form     the same workload in the FP64 GPU form, and the speedup.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle pushes/s (gather+push+deposit) at 1 GPU; % HBM roofline vs FP64 form"
+HBM_PEAK_GBS = 8000.0
+PMC_FILE = os.path.join(ROOT, "profiles", "push_kernel_thermal64_pmc.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1308_5892_amd", "csrc", "pic_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def pmc_traffic():
+    """Counter-based HBM bytes per push launch from the committed summary, or
+    None when it is missing or was taken on another version of the kernel."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    kv = {}
+    for line in open(PMC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_sha():
+        return None
+    try:
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_sim(w, fp64, tile, sort_interval):
+    from paper_1308_5892_amd import pic as P
+    cells = w["dims"][0] * w["dims"][1] * w["dims"][2]
+    npairs = w["ppc"] * cells
+    box = {"n": w["dims"], "n_x": w["n_x"], "rho0": 2.0 * w["ppc"], "max_particles": [npairs, npairs],
+           "tile": tile}
+    sim = P.Simulation([box], [(-1.0, 1.0), (1.0, 1.0)], w["dt"], fp64=fp64, sort_interval=sort_interval)
+    sim.load(0, 0, 1, (w["theta"], 0.0, 1), (w["theta"], 0.0, 1), w["ppc"], seed=w["seed"])
+    sim.step(0)  # bin the loaded pairs and integrate u back by dt/2
+    return sim, 2 * npairs, cells
+
+
+def time_form(w, fp64, steps, warmup, tile, sort_interval):
+    import torch
+    from paper_1308_5892_amd import pic as P
+    sim, npart, cells = make_sim(w, fp64, tile, sort_interval)
+    torch.cuda.synchronize()
+    if warmup:
+        sim.step(warmup)
+    torch.cuda.synchronize()
+    P.pic_set_timing(sim.ctx, 1)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = P.pic_get_timing(sim.ctx)
+    d = sim.diag(0)
+    sim.close()
+    return {"seconds": t1 - t0, "npart": npart, "cells": cells, "timing": tm, "diag": d}
+
+
+def cpu_baseline(w):
+    """The FP64 oracle, single-threaded, on 32^3 cells at the workload's density
+    and temperature: pushes per second over 2 full steps."""
+    from oracle import oracle as O
+    dims = (32, 32, 32)
+    npairs = w["ppc"] * 32 ** 3
+    sp = {"theta": w["theta"], "gb": 0.0, "axis": 1}
+    x, ua, ub = O.load_pairs(dims, w["seed"], 0, npairs, sp, sp)
+    st = O.State(dims, w["dt"], w["n_x"], 2.0 * w["ppc"], [(-1.0, 1.0), (1.0, 1.0)])
+    st.add_particles(0, x, ua)
+    st.add_particles(1, x, ub)
+    nsteps = 2
+    t0 = time.perf_counter()
+    st.step(nsteps)
+    dt = time.perf_counter() - t0
+    return {"value": 2 * npairs * nsteps / dt, "unit": "pushes/s", "cores": 1, "kind": "oracle",
+            "sample": f"32^3 cells at {w['ppc']} pairs/cell, theta={w['theta']}, {nsteps} full steps "
+                      f"({2 * npairs * nsteps} pushes, {dt:.1f} s), single thread"}
+
+
+def copy_calibration(nbytes):
+    """A plain device copy of known size, for scaling the FETCH_SIZE/WRITE_SIZE
+    counters of a --pmc run."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 copies of {nbytes} bytes")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--tile", type=int, nargs=3, default=(4, 4, 4))
+    ap.add_argument("--sort-interval", type=int, default=50)
+    ap.add_argument("--fp64-steps", type=int, default=40)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU form")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="also run a plain copy of BYTES bytes (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import pic_inputs as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = W.THERMAL64
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+
+    log(f"FP32 form: {w['name']}, {args.warmup} warmup + {args.steps} timed steps")
+    r32 = time_form(w, False, args.steps, args.warmup, tuple(args.tile), args.sort_interval)
+    npart, cells = r32["npart"], r32["cells"]
+    value = npart * args.steps / r32["seconds"]
+    tm = r32["timing"]
+    push_avg_s = tm["push_ms"] / max(1, tm["push_launches"]) / 1e3
+    # algorithmic bytes of one push launch: particle state read + written (28 B
+    # each way), node-field read (6 x 4 B) and current flush (3 x 8 B) per cell
+    push_bytes = 56.0 * npart + 48.0 * cells
+    achieved = push_bytes / push_avg_s / 1e9
+    traffic = pmc_traffic()
+    step_bytes = 56.0 * npart + 144.0 * cells
+    log(f"FP32: {value / 1e9:.2f} G pushes/s, push kernel {push_avg_s * 1e3:.3f} ms "
+        f"({achieved:.0f} GB/s), fields {tm['field_ms'] / max(1, tm['field_launches']):.3f} ms/step, "
+        f"sort {tm['sort_ms']:.1f} ms total")
+
+    fp64 = None
+    if not args.no_fp64:
+        log(f"FP64 form: {args.fp64_steps} timed steps")
+        r64 = time_form(w, True, args.fp64_steps, 5, tuple(args.tile), args.sort_interval)
+        v64 = r64["npart"] * args.fp64_steps / r64["seconds"]
+        t64 = r64["timing"]
+        p64 = t64["push_ms"] / max(1, t64["push_launches"]) / 1e3
+        b64 = 104.0 * npart + 96.0 * cells   # 52 B state each way, 6 x 8 B fields, 3 x 8 B current
+        fp64 = {"value": v64, "unit": "pushes/s", "steps": args.fp64_steps,
+                "push_kernel_ms": p64 * 1e3, "roofline_frac": b64 / p64 / 1e9 / HBM_PEAK_GBS,
+                "speedup_fp32_over_fp64": value / v64}
+        log(f"FP64: {v64 / 1e9:.2f} G pushes/s, speedup {value / v64:.2f}x")
+
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline (bounded sample)")
+        cpu = cpu_baseline(w)
+        log(f"CPU: {cpu['value'] / 1e6:.2f} M pushes/s")
+
+    d = r32["diag"]
+    out = {
+        "metric": METRIC, "value": value, "unit": "pushes/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r32["seconds"] / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w["name"] + ", 64 pairs/cell, theta=0.1, dt=0.5, n_x=10",
+                   "cells": cells, "particles": npart, "tile": list(args.tile),
+                   "sort_interval": args.sort_interval, "current": "int64 fixed point, 2^-31"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "push_kernel<float> (gather+push+deposit)",
+                     "bytes_per_launch": push_bytes, "avg_launch_ms": push_avg_s * 1e3,
+                     "whole_step_frac": value * step_bytes / npart / 1e9 / HBM_PEAK_GBS},
+        "cpu_baseline": cpu,
+        "fp64_form": fp64,
+        "check": {"flags": d["flags"], "particles": int(d["count"].sum()),
+                  "gauss_max": d["gauss_max"], "overflow": int(d["n_overflow"].sum())},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,258 @@
+/*
+ * pic.h - C ABI of the MI355X (gfx950) hot path of the explicit relativistic
+ * particle-in-cell cycle of Melzani et al., "Apar-T" (arXiv:1308.5892).
+ *
+ * One step is the leap-frog cycle of App. A.3.1: field gather from the
+ * staggered Yee grid (App. A.3.3), relativistic Boris push and move (App. A.3.3,
+ * eq. mover), charge-conserving volume-weighting current deposit (App. A.1 and
+ * A.3.4, eq. current_dep) and the Yee update of b and e (App. A.3.2), with
+ * periodic boundaries (App. A.4).  The current filter of item 10 is not applied.
+ *
+ * Units are the paper's normalised ones (App. A.2): lengths in cells (dx = 1),
+ * times in X0/c, e and b = cB in m_e c^2/(e X0), u = gamma v / c.  Species s has
+ * charge q_s = +-e (Sect. 2.1) and mass m_s; it moves with k_s = (q_s/e)(m_e/m_s)
+ * and feeds e through alpha_s = 2 sgn(q_s) / (n_x^2 rho0) (App. A.2, eq. alpha).
+ *
+ * State and time levels follow App. A.3.1: between calls the library holds
+ * positions x and e at time t, momenta u and b at t - dt/2.
+ *
+ * Grid layout (App. A.3.2, A.3.3): box of n[0] x n[1] x n[2] cells, nodes at
+ * integer points; e_x[i,j,k] at (i+1/2, j, k), e_y at (i, j+1/2, k), e_z at
+ * (i, j, k+1/2); b_x at (i, j+1/2, k+1/2), b_y at (i+1/2, j, k+1/2), b_z at
+ * (i+1/2, j+1/2, k); j_c where e_c sits.  Host field arrays are FP64,
+ * component-major, cell index i + n0 (j + n1 k): value (c, i, j, k) at
+ * [c * n0 n1 n2 + i + n0 (j + n1 k)].
+ *
+ * Memory and ownership: the caller allocates ONE device buffer (the arena, size
+ * from pic_plan, 256-byte aligned) and owns the HIP stream; the library carves
+ * all device state out of the arena, allocates no device memory itself, and
+ * enqueues all work on that stream.  Both must outlive the context.  Host
+ * buffers passed to get/set calls belong to the caller and are copied.
+ *
+ * Errors: every call returns PIC_OK (0) or a negative PIC_E* code;
+ * pic_last_error(ctx) gives a message for the last failure on that context.
+ * Kernels record faults (non-finite momentum, lost particle) in a device flag
+ * word that the next pic_diag or pic_sync reports as PIC_EFLAG.
+ *
+ * Limits: n[0], n[1] <= 2048, n[2] <= 1024; tile edges are powers of two
+ * between 1 and 8; at most PIC_MAX_SPECIES species; fewer than 2^31 particles
+ * per species per box; dt < 1/sqrt(3) (3-D Courant bound of the Yee scheme).
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_OK        0
+#define PIC_EINVAL   (-1)  /* bad argument or configuration */
+#define PIC_ECOURANT (-2)  /* dt violates a stability bound (App. B) */
+#define PIC_ENOMEM   (-3)  /* arena too small or particle capacity exceeded */
+#define PIC_EDEVICE  (-4)  /* a HIP runtime call failed */
+#define PIC_EFLAG    (-5)  /* a kernel raised the device error flag */
+#define PIC_ESTATE   (-6)  /* call not valid in the current state */
+
+#define PIC_MAX_SPECIES 4
+
+/* pic_config.flags */
+#define PIC_FP64_FORM 1u   /* FP64 storage and arithmetic, FP64 atomics (reference form) */
+#define PIC_TRACK_IDS 2u   /* carry a 32-bit particle id (parity and checkpoints) */
+
+/* pic_load_desc.profile */
+#define PIC_PROFILE_UNIFORM 0
+#define PIC_PROFILE_HARRIS  1
+
+/* device error flag bits, reported through pic_diag_out.flags */
+#define PIC_FLAG_NONFINITE 1u  /* a momentum became NaN or infinite */
+#define PIC_FLAG_LOST      2u  /* a tile segment and the overflow region were full */
+
+typedef struct pic_species {
+    double q_over_e;   /* +1 or -1 (Sect. 2.1: superparticles of ions or electrons) */
+    double m_over_me;  /* mass in electron masses */
+} pic_species;
+
+typedef struct pic_box {
+    int32_t n[3];                             /* cells per axis */
+    double  n_x;                              /* cells per reference skin depth (Sect. 2.2.1) */
+    double  rho0;                             /* reference superparticles per cell, all species (eq. neandrho) */
+    int64_t max_particles[PIC_MAX_SPECIES];   /* capacity per species */
+    int32_t tile[3];                          /* tile edge per axis, power of two in [1, 8]; 0 = 4 */
+} pic_box;
+
+typedef struct pic_config {
+    int32_t            n_boxes;     /* independent periodic boxes advanced together */
+    const pic_box     *boxes;       /* n_boxes entries (copied) */
+    int32_t            n_species;   /* same species list in every box */
+    pic_species        species[PIC_MAX_SPECIES];
+    double             dt;          /* time step in X0/c */
+    int32_t            sort_interval;  /* steps between counting-sort repacks; 0 = never */
+    uint32_t           flags;       /* PIC_FP64_FORM | PIC_TRACK_IDS */
+    int32_t            hist_bins;   /* bins of the log10(gamma-1) histogram in pic_diag (0 = none) */
+    double             hist_lo, hist_hi;   /* histogram range of log10(gamma - 1) */
+    double             headroom;    /* particle slots per particle (>= 1.05; 0 = 1.3) */
+} pic_config;
+
+/* One drifting Maxwell-Juttner population (Sect. 4.3, eq. Jutt). */
+typedef struct pic_mj {
+    double  theta;        /* T / (m_s c^2) */
+    double  gamma_beta;   /* signed Gamma0 beta0 of the drift (0: at rest) */
+    int32_t axis;         /* drift axis 0, 1, 2 */
+} pic_mj;
+
+/*
+ * A load of co-located pairs (Sect. 2.1): species_a and species_b particles on
+ * top of each other so that the charge density stays zero, momenta drawn from
+ * two drifting Maxwell-Juttner distributions (Sect. 4.3; App. D).  ppc is the
+ * number of pairs per cell at the profile's peak in the simulation frame.
+ * UNIFORM: round(ppc * cells) pairs, positions uniform in the box.  HARRIS:
+ * density ~ 1/cosh^2((s - centre)/thickness) along profile_axis (App. C) on the
+ * window |s - centre| < half_width, round(ppc * (cells/n[axis]) * 2 thickness
+ * tanh(half_width/thickness)) pairs, other coordinates uniform.
+ * Random numbers: Philox4x64-10 with key (seed, stream) and counter
+ * (pair, j, 0, 0); the mapping of the twelve words per pair is fixed.
+ */
+typedef struct pic_load_desc {
+    int32_t  box;
+    int32_t  species_a, species_b;
+    pic_mj   mj_a, mj_b;
+    double   ppc;
+    int32_t  profile;         /* PIC_PROFILE_UNIFORM or PIC_PROFILE_HARRIS */
+    int32_t  profile_axis;
+    double   centre, thickness, half_width;
+    uint64_t seed, stream;
+} pic_load_desc;
+
+/* Harris-sheet magnetic field (App. C, eq. B_field_Harris) on one box. */
+typedef struct pic_harris_field {
+    int32_t box;
+    int32_t grad_axis;   /* axis along which the field varies */
+    int32_t field_axis;  /* component of b that is set (!= grad_axis) */
+    int32_t n_sheets;    /* 1: b = b0 tanh((s-c0)/L); 2: b = b0 [tanh((s-c0)/L) - tanh((s-c1)/L) - 1] */
+    double  b0, thickness;
+    double  centre[2];
+} pic_harris_field;
+
+typedef struct pic_diag_out {
+    double  t;                          /* simulation time of x and e */
+    int64_t step;
+    double  W_E[3], W_B[3];             /* (1/alpha0) sum_cells e_c^2/2 and (b^t)_c^2/2 */
+    double  K[PIC_MAX_SPECIES];         /* sum (m_s/m_e)(gamma^t - 1) */
+    double  P[PIC_MAX_SPECIES][3];      /* sum of u^- = u^{t-dt/2} + (k dt/2) E(x^t) */
+    double  sum_gm1[PIC_MAX_SPECIES];   /* sum (gamma^t - 1) */
+    int64_t n_particles[PIC_MAX_SPECIES];
+    int64_t n_overflow[PIC_MAX_SPECIES];   /* particles in the overflow region */
+    double  gauss_max, gauss_rms;       /* |div e - rho| over the nodes, rho = sum alpha_s W(x_p) */
+    uint32_t flags;                     /* PIC_FLAG_* raised since the last report */
+} pic_diag_out;
+
+typedef struct pic_ctx pic_ctx;
+
+/*
+ * Size of the device arena that pic_init needs for cfg.  Validates cfg;
+ * returns PIC_EINVAL with *arena_bytes untouched on a bad configuration.
+ */
+int pic_plan(const pic_config *cfg, size_t *arena_bytes);
+
+/*
+ * Create a context.  dev_arena: device pointer of at least pic_plan bytes
+ * (borrowed).  hip_stream: hipStream_t to enqueue on (borrowed; NULL = default).
+ * Checks the 3-D Courant bound dt < 1/sqrt(3) (App. B states the bound as
+ * dt < X0/sqrt 2, which is the 2-D one) and omega_pe dt = dt/n_x < 2 (App. B),
+ * returning PIC_ECOURANT.  Zeroes all fields and particles.
+ */
+int pic_init(const pic_config *cfg, void *dev_arena, size_t bytes, void *hip_stream,
+             pic_ctx **out);
+
+/*
+ * Load a pair population (see pic_load_desc).  FP64 on the device: inverse-CDF
+ * table of the p_y marginal (App. D, eq. distr_y), Newton solve for u
+ * (App. D, eq. finding_u), rounding to the storage format.  The particles are
+ * binned, and their momenta integrated back by dt/2 in the fields of that
+ * moment (App. A.3.1), at the next pic_step or pic_diag.  Asynchronous.
+ * PIC_ENOMEM if the species capacity would be exceeded.
+ */
+int pic_load_maxwell_juttner(pic_ctx *ctx, const pic_load_desc *d);
+
+/*
+ * Set the Harris-sheet b (App. C) at t = 0 and shift it to the stored time
+ * level: b^{-dt/2} = b^0 + (dt/2) curl e^0.  Other components are unchanged.
+ */
+int pic_set_harris_field(pic_ctx *ctx, const pic_harris_field *h);
+
+/*
+ * Enqueue n full cycles of App. A.3.1 on the stream for every box.  Does not
+ * synchronise; kernel faults surface in the next pic_diag / pic_sync.
+ */
+int pic_step(pic_ctx *ctx, int n);
+
+/*
+ * FP64 diagnostics of box `box` at the current time (synchronises):
+ * field energies per component, kinetic energy and k = 0 momentum per species,
+ * the gamma-1 histogram (hist: caller array of n_species * hist_bins int64, or
+ * NULL), and the Gauss-law residual.  Returns PIC_EFLAG (after filling *out)
+ * if the device error flag was raised; the flag is then cleared.
+ */
+int pic_diag(pic_ctx *ctx, int box, pic_diag_out *out, int64_t *hist);
+
+/*
+ * Copy particles of (box, species) to the host as FP64: x[3n] absolute
+ * positions in [0, n_axis), u[3n], id[n] (NULL allowed; zeros without
+ * PIC_TRACK_IDS).  *n: in = capacity of the arrays, out = particle count
+ * (PIC_ENOMEM if too small).  With PIC_TRACK_IDS the output is ordered by id.
+ * Synchronises.
+ */
+int pic_get_particles(pic_ctx *ctx, int box, int species, double *x, double *u,
+                      int32_t *id, int64_t *n);
+
+/*
+ * Replace all particles of (box, species) by n given ones (x^t, u^{t-dt/2};
+ * no half step is applied).  Positions are wrapped into the box and rounded to
+ * the storage format.  id may be NULL (ids 0..n-1).
+ */
+int pic_set_particles(pic_ctx *ctx, int box, int species, const double *x, const double *u,
+                      const int32_t *id, int64_t n);
+
+/* Copy e^t, b^{t-dt/2} and the pending current (NULLs allowed) to the host. */
+int pic_get_fields(pic_ctx *ctx, int box, double *e, double *b, double *j);
+
+/* Set e^t and b^{t-dt/2} of a box (NULL leaves that field unchanged). */
+int pic_set_fields(pic_ctx *ctx, int box, const double *e, const double *b);
+
+/* Kernel timing of pic_step, from HIP events recorded on the context's stream
+ * right before and after each launch (measurement hook, off by default). */
+typedef struct pic_timing {
+    int64_t push_launches;   /* fused gather + push + deposit kernel */
+    double  push_ms;
+    int64_t field_launches;  /* Yee b and e updates (one pair per step) */
+    double  field_ms;
+    int64_t sort_launches;   /* counting-sort repacks */
+    double  sort_ms;
+} pic_timing;
+
+/* Turn event recording in pic_step on (1) or off (0). */
+int pic_set_timing(pic_ctx *ctx, int enable);
+
+/* Sum the recorded intervals into *out (synchronises); reset != 0 forgets them. */
+int pic_get_timing(pic_ctx *ctx, pic_timing *out, int reset);
+
+/* Wait for the stream; returns PIC_EFLAG if the device error flag is set. */
+int pic_sync(pic_ctx *ctx);
+
+/* Number of completed steps. */
+int64_t pic_steps_done(const pic_ctx *ctx);
+
+/* Release the context (the arena and stream stay the caller's). */
+int pic_free(pic_ctx *ctx);
+
+/* Message of the last error on ctx (static storage of the context). */
+const char *pic_last_error(const pic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

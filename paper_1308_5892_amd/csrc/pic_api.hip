@@ -1,0 +1,901 @@
+// Host side of the C ABI declared in include/pic.h: arena layout, context,
+// stream-ordered launches of the gfx950 kernels, and host<->device copies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "pic_internal.h"
+
+namespace pic {
+
+constexpr int kTabN = 1 << 16;     // inverse-CDF table intervals
+constexpr int kTabM = 1 << 16;     // quadrature intervals behind the table
+
+// ------------------------------------------------------------ arena layout
+
+struct Bump {
+    char *base;
+    size_t off = 0;
+    template <typename T> T *take(size_t n)
+    {
+        off = (off + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+static int ilog2(int v)
+{
+    int s = 0;
+    while ((1 << s) < v) ++s;
+    return s;
+}
+
+struct BoxHost {
+    pic_box cfg;
+    int tile[3];
+    int64_t nc;
+    int ntiles;
+    int32_t slots[kMaxSpecies], ovf_cap[kMaxSpecies], stage_cap[kMaxSpecies];
+};
+
+template <typename R>
+static void carve(Bump &A, const pic_config *cfg, std::vector<BoxHost> &bh, std::vector<BoxDev<R>> &bd)
+{
+    using JT = typename JType<R>::T;
+    const bool ids = (cfg->flags & PIC_TRACK_IDS) != 0;
+    for (int b = 0; b < cfg->n_boxes; ++b) {
+        BoxHost &H = bh[b];
+        BoxDev<R> &D = bd[b];
+        for (int a = 0; a < 3; ++a) {
+            D.n[a] = H.cfg.n[a];
+            D.tshift[a] = ilog2(H.tile[a]);
+            D.ntile[a] = (H.cfg.n[a] + H.tile[a] - 1) / H.tile[a];
+        }
+        D.ntiles = H.ntiles;
+        D.nc = H.nc;
+        D.e = A.take<R>(3 * H.nc);
+        D.b = A.take<R>(3 * H.nc);
+        D.J = A.take<JT>(3 * H.nc);
+        D.rho = A.take<double>(H.nc);
+        D.acc = A.take<double>(kAccLen);
+        D.hist = A.take<int64_t>((size_t)std::max(1, cfg->hist_bins) * kMaxSpecies);
+        D.alpha0 = 2.0 / (H.cfg.n_x * H.cfg.n_x * H.cfg.rho0);
+        for (int s = 0; s < kMaxSpecies; ++s) {
+            SpeciesDev<R> &S = D.sp[s];
+            memset(&S, 0, sizeof(S));
+            if (s >= cfg->n_species) continue;
+            const size_t n = H.slots[s], ns = H.stage_cap[s];
+            for (int c = 0; c < 2; ++c) {
+                S.buf[c].cell = A.take<int32_t>(n);
+                for (int a = 0; a < 3; ++a) S.buf[c].d[a] = A.take<R>(n);
+                for (int a = 0; a < 3; ++a) S.buf[c].u[a] = A.take<R>(n);
+                S.buf[c].id = ids ? A.take<int32_t>(n) : nullptr;
+            }
+            S.stage.cell = A.take<int32_t>(ns);
+            for (int a = 0; a < 3; ++a) S.stage.d[a] = A.take<R>(ns);
+            for (int a = 0; a < 3; ++a) S.stage.u[a] = A.take<R>(ns);
+            S.stage.id = ids ? A.take<int32_t>(ns) : nullptr;
+            for (int c = 0; c < 2; ++c) {
+                S.seg_start[c] = A.take<int32_t>(H.ntiles + 1);
+                S.seg_cap[c] = A.take<int32_t>(H.ntiles + 1);
+            }
+            S.cnt[0] = A.take<int32_t>(H.ntiles + 1);
+            S.cnt[1] = A.take<int32_t>(H.ntiles + 1);
+            S.tcount = A.take<int32_t>(H.ntiles + 1);
+            S.slots = H.slots[s];
+            S.ovf_cap = H.ovf_cap[s];
+        }
+    }
+}
+
+static int validate(const pic_config *cfg, std::vector<BoxHost> &bh, std::string &err)
+{
+    if (!cfg || cfg->n_boxes < 1 || !cfg->boxes) { err = "need at least one box"; return PIC_EINVAL; }
+    if (cfg->n_species < 1 || cfg->n_species > kMaxSpecies) { err = "n_species out of range"; return PIC_EINVAL; }
+    for (int s = 0; s < cfg->n_species; ++s) {
+        if (std::fabs(std::fabs(cfg->species[s].q_over_e) - 1.0) > 0 || !(cfg->species[s].m_over_me > 0)) {
+            err = "species charge must be +-e and mass positive";
+            return PIC_EINVAL;
+        }
+    }
+    if (!(cfg->dt > 0)) { err = "dt must be positive"; return PIC_EINVAL; }
+    if (cfg->hist_bins < 0 || (cfg->hist_bins > 0 && !(cfg->hist_hi > cfg->hist_lo))) {
+        err = "bad histogram range";
+        return PIC_EINVAL;
+    }
+    const double hr = cfg->headroom > 0 ? cfg->headroom : 1.3;
+    if (hr < 1.05) { err = "headroom must be >= 1.05"; return PIC_EINVAL; }
+    bh.resize(cfg->n_boxes);
+    for (int b = 0; b < cfg->n_boxes; ++b) {
+        BoxHost &H = bh[b];
+        H.cfg = cfg->boxes[b];
+        const int lim[3] = {2048, 2048, 1024};
+        for (int a = 0; a < 3; ++a) {
+            if (H.cfg.n[a] < 1 || H.cfg.n[a] > lim[a]) { err = "box size out of range"; return PIC_EINVAL; }
+            int t = H.cfg.tile[a] ? H.cfg.tile[a] : 4;
+            if (t < 1 || t > 8 || (t & (t - 1))) { err = "tile edge must be 1, 2, 4 or 8"; return PIC_EINVAL; }
+            H.tile[a] = t;
+        }
+        if (!(H.cfg.n_x > 0) || !(H.cfg.rho0 > 0)) { err = "n_x and rho0 must be positive"; return PIC_EINVAL; }
+        H.nc = (int64_t)H.cfg.n[0] * H.cfg.n[1] * H.cfg.n[2];
+        H.ntiles = 1;
+        for (int a = 0; a < 3; ++a) H.ntiles *= (H.cfg.n[a] + H.tile[a] - 1) / H.tile[a];
+        for (int s = 0; s < cfg->n_species; ++s) {
+            const int64_t mp = H.cfg.max_particles[s];
+            if (mp < 0) { err = "negative capacity"; return PIC_EINVAL; }
+            const int64_t ovf = std::max<int64_t>(1024, mp / 16);
+            const int64_t slots = (int64_t)std::ceil(mp * hr) + 32 * (int64_t)H.ntiles + ovf;
+            if (slots >= (int64_t)1 << 31) { err = "more than 2^31 particle slots in one species"; return PIC_EINVAL; }
+            H.slots[s] = (int32_t)slots;
+            H.ovf_cap[s] = (int32_t)ovf;
+            H.stage_cap[s] = (int32_t)std::max<int64_t>(mp, 1);
+        }
+    }
+    return PIC_OK;
+}
+
+struct Layout {
+    void *boxes = nullptr;
+    Item *items_push = nullptr, *items_box = nullptr;
+    CellBlock *cblocks = nullptr;
+    StageItem *sitems = nullptr;
+    uint32_t *flags = nullptr;
+    double *mj_cum = nullptr, *mj_tab[2] = {nullptr, nullptr};
+    int n_items = 0, n_cblocks = 0, max_sitems = 0;
+    size_t bytes = 0;
+};
+
+template <typename R>
+static void make_layout(const pic_config *cfg, std::vector<BoxHost> &bh, char *base, Layout &L,
+                        std::vector<BoxDev<R>> &bd)
+{
+    Bump A{base};
+    L.boxes = A.take<BoxDev<R>>(cfg->n_boxes);
+    L.n_items = 0;
+    L.n_cblocks = 0;
+    L.max_sitems = 0;
+    for (auto &H : bh) {
+        L.n_items += H.ntiles + kOvfBlocks;
+        L.n_cblocks += (int)((H.nc + kBlock - 1) / kBlock);
+        for (int s = 0; s < cfg->n_species; ++s) L.max_sitems += (H.stage_cap[s] + kBlock - 1) / kBlock;
+    }
+    L.items_push = A.take<Item>(L.n_items);
+    L.items_box = A.take<Item>(L.n_items);
+    L.cblocks = A.take<CellBlock>(L.n_cblocks);
+    L.sitems = A.take<StageItem>(std::max(1, L.max_sitems));
+    L.flags = A.take<uint32_t>(64);
+    L.mj_cum = A.take<double>(kTabM + 1);
+    L.mj_tab[0] = A.take<double>(kTabN + 1);
+    L.mj_tab[1] = A.take<double>(kTabN + 1);
+    bd.resize(cfg->n_boxes);
+    carve<R>(A, cfg, bh, bd);
+    L.bytes = ((A.off + 255) & ~size_t(255)) + 256;
+}
+
+} // namespace pic
+
+using namespace pic;
+
+struct pic_ctx {
+    pic_config cfg;
+    std::vector<pic_box> boxes;
+    std::vector<BoxHost> bh;
+    bool fp64 = false;
+    hipStream_t stream = nullptr;
+    char *arena = nullptr;
+    Layout L;
+    std::vector<BoxDev<float>> bd32;
+    std::vector<BoxDev<double>> bd64;
+    std::vector<int> box_item_off;          // first item of each box in items_box
+    std::vector<int> box_cblock_off;        // first cell block of each box
+    std::vector<std::vector<int32_t>> stage_n, stage_half, next_id;
+    int cur = 0;
+    int64_t step = 0;
+    size_t lds_bytes = 0;
+    bool pending = false;
+    uint32_t flags_seen = 0;
+    std::string err;
+    // timing hook: event pairs per kind (0 push, 1 fields, 2 sort)
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
+    std::vector<hipEvent_t> ev_pool;
+    ~pic_ctx()
+    {
+        for (auto &v : ev)
+            for (auto &p : v) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
+        for (auto e : ev_pool) hipEventDestroy(e);
+    }
+};
+
+static hipEvent_t take_event(pic_ctx *ctx)
+{
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// record the start (begin = true) or the end of a timed launch of kind k
+static void mark(pic_ctx *ctx, int k, bool begin)
+{
+    if (!ctx->timing) return;
+    if (begin) {
+        hipEvent_t a = take_event(ctx);
+        if (!a) return;
+        hipEventRecord(a, ctx->stream);
+        ctx->ev[k].push_back({a, nullptr});
+    } else if (!ctx->ev[k].empty() && !ctx->ev[k].back().second) {
+        hipEvent_t b = take_event(ctx);
+        if (!b) return;
+        hipEventRecord(b, ctx->stream);
+        ctx->ev[k].back().second = b;
+    }
+}
+
+template <typename R> static std::vector<BoxDev<R>> &bdvec(pic_ctx *ctx);
+template <> std::vector<BoxDev<float>> &bdvec<float>(pic_ctx *ctx) { return ctx->bd32; }
+template <> std::vector<BoxDev<double>> &bdvec<double>(pic_ctx *ctx) { return ctx->bd64; }
+
+#define HIPCHK(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);              \
+            return PIC_EDEVICE;                                                        \
+        }                                                                              \
+    } while (0)
+
+template <typename R>
+static StepConst<R> step_const(pic_ctx *ctx)
+{
+    StepConst<R> C;
+    memset(&C, 0, sizeof(C));
+    C.dt = (R)ctx->cfg.dt;
+    C.nsp = ctx->cfg.n_species;
+    for (int s = 0; s < C.nsp; ++s) {
+        const pic_species &S = ctx->cfg.species[s];
+        C.kq[s] = (R)(S.q_over_e / S.m_over_me);   // (q/e)(m_e/m), App. A.2
+        C.qs[s] = (R)(S.q_over_e > 0 ? 1 : -1);
+        C.mass[s] = (R)S.m_over_me;
+    }
+    C.flags = ctx->L.flags;
+    C.cur = ctx->cur;
+    C.hist_bins = ctx->cfg.hist_bins;
+    C.hist_lo = ctx->cfg.hist_lo;
+    C.hist_hi = ctx->cfg.hist_hi;
+    return C;
+}
+
+// bin staged particles (and refresh the layout of the binned ones)
+template <typename R>
+static int merge_t(pic_ctx *ctx, bool force)
+{
+    if (!ctx->pending && !force) return PIC_OK;
+    std::vector<StageItem> si;
+    for (int b = 0; b < ctx->cfg.n_boxes; ++b)
+        for (int s = 0; s < ctx->cfg.n_species; ++s)
+            for (int f = 0; f < ctx->stage_n[b][s]; f += kBlock)
+                si.push_back({b, s, f, std::min(ctx->stage_n[b][s], f + kBlock), ctx->stage_half[b][s]});
+    if ((int)si.size() > ctx->L.max_sitems) { ctx->err = "stage item list overflow"; return PIC_ENOMEM; }
+    if (!si.empty()) {
+        HIPCHK(hipMemcpyAsync(ctx->L.sitems, si.data(), si.size() * sizeof(StageItem), hipMemcpyHostToDevice,
+                              ctx->stream));
+    }
+    StepConst<R> C = step_const<R>(ctx);
+    HIPCHK(launch_repack<R>(reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes), ctx->cfg.n_boxes, ctx->L.items_box,
+                            ctx->L.n_items, ctx->L.sitems, (int)si.size(), C, ctx->stream));
+    ctx->cur ^= 1;
+    for (auto &v : ctx->stage_n) std::fill(v.begin(), v.end(), 0);
+    ctx->pending = false;
+    if (!si.empty()) HIPCHK(hipStreamSynchronize(ctx->stream));   // the host stage list must outlive the copy
+    return PIC_OK;
+}
+
+static int merge(pic_ctx *ctx, bool force = false)
+{
+    return ctx->fp64 ? merge_t<double>(ctx, force) : merge_t<float>(ctx, force);
+}
+
+template <typename R>
+static int init_t(pic_ctx *ctx)
+{
+    std::vector<BoxDev<R>> &bd = bdvec<R>(ctx);
+    make_layout<R>(&ctx->cfg, ctx->bh, ctx->arena, ctx->L, bd);
+    HIPCHK(hipMemsetAsync(ctx->arena, 0, ctx->L.bytes - 256, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->L.boxes, bd.data(), bd.size() * sizeof(BoxDev<R>), hipMemcpyHostToDevice, ctx->stream));
+    // work items: per box its tiles then its overflow sweeps (box order), and
+    // the same list permuted so that consecutive tiles land on one XCD
+    // (blocks are dealt round-robin over the 8 XCDs of the MI355X)
+    std::vector<Item> items;
+    std::vector<CellBlock> cbs;
+    for (int b = 0; b < ctx->cfg.n_boxes; ++b) {
+        ctx->box_item_off.push_back((int)items.size());
+        for (int t = 0; t < ctx->bh[b].ntiles; ++t) items.push_back({b, t});
+        for (int k = 0; k < kOvfBlocks; ++k) items.push_back({b, -1 - k});
+        ctx->box_cblock_off.push_back((int)cbs.size());
+        for (int64_t f = 0; f < ctx->bh[b].nc; f += kBlock) cbs.push_back({b, (int32_t)f});
+    }
+    ctx->box_item_off.push_back((int)items.size());
+    ctx->box_cblock_off.push_back((int)cbs.size());
+    const int n = (int)items.size();
+    std::vector<Item> perm(n);
+    {
+        const int X = 8;
+        const int per = (n + X - 1) / X;
+        int g = 0;
+        std::vector<int> used(n, 0);
+        for (int blk = 0; blk < n; ++blk) {
+            // block blk runs on XCD blk % 8; give that XCD the next item of its chunk
+            const int x = blk % X, slot = blk / X;
+            int src = x * per + slot;
+            if (src >= n || used[src]) {   // ragged tail: first unused item
+                while (used[g]) ++g;
+                src = g;
+            }
+            used[src] = 1;
+            perm[blk] = items[src];
+        }
+    }
+    HIPCHK(hipMemcpyAsync(ctx->L.items_box, items.data(), n * sizeof(Item), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->L.items_push, perm.data(), n * sizeof(Item), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->L.cblocks, cbs.data(), cbs.size() * sizeof(CellBlock), hipMemcpyHostToDevice,
+                          ctx->stream));
+    size_t lds = 0;
+    for (auto &H : ctx->bh) lds = std::max(lds, push_lds_bytes<R>(H.tile[0], H.tile[1], H.tile[2]));
+    ctx->lds_bytes = lds;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    // initial segment layout: an empty repack
+    return merge_t<R>(ctx, true);
+}
+
+// The exported functions take their C linkage from their declarations in pic.h.
+
+int pic_plan(const pic_config *cfg, size_t *arena_bytes)
+{
+    std::vector<BoxHost> bh;
+    std::string err;
+    int rc = validate(cfg, bh, err);
+    if (rc) return rc;
+    if (!arena_bytes) return PIC_EINVAL;
+    Layout L;
+    if (cfg->flags & PIC_FP64_FORM) {
+        std::vector<BoxDev<double>> bd;
+        make_layout<double>(cfg, bh, nullptr, L, bd);
+    } else {
+        std::vector<BoxDev<float>> bd;
+        make_layout<float>(cfg, bh, nullptr, L, bd);
+    }
+    *arena_bytes = L.bytes;
+    return PIC_OK;
+}
+
+int pic_init(const pic_config *cfg, void *dev_arena, size_t bytes, void *hip_stream, pic_ctx **out)
+{
+    if (!out) return PIC_EINVAL;
+    *out = nullptr;
+    pic_ctx *ctx = new (std::nothrow) pic_ctx;
+    if (!ctx) return PIC_ENOMEM;
+    std::string err;
+    int rc = validate(cfg, ctx->bh, err);
+    if (rc) { delete ctx; return rc; }
+    // stability (App. B): Courant for the 3-D Yee scheme, and omega_pe dt < 2
+    if (!(cfg->dt < 1.0 / std::sqrt(3.0))) { delete ctx; return PIC_ECOURANT; }
+    for (auto &H : ctx->bh)
+        if (!(cfg->dt / H.cfg.n_x < 2.0)) { delete ctx; return PIC_ECOURANT; }
+    size_t need = 0;
+    pic_plan(cfg, &need);
+    if (!dev_arena || bytes < need) { delete ctx; return PIC_ENOMEM; }
+    if (reinterpret_cast<uintptr_t>(dev_arena) & 255) { delete ctx; return PIC_EINVAL; }
+    ctx->cfg = *cfg;
+    ctx->boxes.assign(cfg->boxes, cfg->boxes + cfg->n_boxes);
+    ctx->cfg.boxes = ctx->boxes.data();
+    ctx->fp64 = (cfg->flags & PIC_FP64_FORM) != 0;
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    ctx->arena = reinterpret_cast<char *>(dev_arena);
+    ctx->stage_n.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
+    ctx->stage_half.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
+    ctx->next_id.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
+    rc = ctx->fp64 ? init_t<double>(ctx) : init_t<float>(ctx);
+    if (rc) {
+        fprintf(stderr, "pic_init: %s\n", ctx->err.c_str());
+        delete ctx;
+        return rc;
+    }
+    *out = ctx;
+    return PIC_OK;
+}
+
+const char *pic_last_error(const pic_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int64_t pic_steps_done(const pic_ctx *ctx) { return ctx ? ctx->step : -1; }
+
+int pic_free(pic_ctx *ctx)
+{
+    if (!ctx) return PIC_EINVAL;
+    delete ctx;
+    return PIC_OK;
+}
+
+static int check_box(pic_ctx *ctx, int box)
+{
+    if (!ctx) return PIC_EINVAL;
+    if (box < 0 || box >= ctx->cfg.n_boxes) { ctx->err = "box index out of range"; return PIC_EINVAL; }
+    return PIC_OK;
+}
+
+static int read_flags(pic_ctx *ctx, uint32_t *out)
+{
+    uint32_t f = 0;
+    HIPCHK(hipMemcpyAsync(&f, ctx->L.flags, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (f) {
+        uint32_t z = 0;
+        HIPCHK(hipMemcpyAsync(ctx->L.flags, &z, sizeof(z), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    *out = f;
+    return PIC_OK;
+}
+
+int pic_sync(pic_ctx *ctx)
+{
+    if (!ctx) return PIC_EINVAL;
+    uint32_t f = 0;
+    int rc = read_flags(ctx, &f);
+    if (rc) return rc;
+    if (f) {
+        ctx->err = "device error flag raised: " + std::to_string(f);
+        return PIC_EFLAG;
+    }
+    return PIC_OK;
+}
+
+template <typename R>
+static int step_t(pic_ctx *ctx, int n)
+{
+    const BoxDev<R> *boxes = reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes);
+    for (int i = 0; i < n; ++i) {
+        StepConst<R> C = step_const<R>(ctx);
+        mark(ctx, 0, true);
+        HIPCHK(launch_push<R>(boxes, ctx->L.items_push, ctx->L.n_items, ctx->lds_bytes, C, ctx->stream));
+        mark(ctx, 0, false);
+        mark(ctx, 1, true);
+        HIPCHK(launch_fields<R>(boxes, ctx->L.cblocks, ctx->L.n_cblocks, (R)ctx->cfg.dt, ctx->cfg.n_species, ctx->cur,
+                                ctx->stream));
+        mark(ctx, 1, false);
+        ctx->cur ^= 1;
+        ctx->step += 1;
+        if (ctx->cfg.sort_interval > 0 && ctx->step % ctx->cfg.sort_interval == 0) {
+            mark(ctx, 2, true);
+            int rc = merge_t<R>(ctx, true);
+            mark(ctx, 2, false);
+            if (rc) return rc;
+        }
+    }
+    return PIC_OK;
+}
+
+int pic_step(pic_ctx *ctx, int n)
+{
+    if (!ctx || n < 0) return PIC_EINVAL;
+    int rc = merge(ctx);
+    if (rc) return rc;
+    return ctx->fp64 ? step_t<double>(ctx, n) : step_t<float>(ctx, n);
+}
+
+template <typename R>
+static int diag_t(pic_ctx *ctx, int box, pic_diag_out *o, int64_t *hist)
+{
+    const BoxDev<R> *boxes = reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes);
+    const BoxDev<R> &D = bdvec<R>(ctx)[box];
+    const int nsp = ctx->cfg.n_species;
+    const int hb = std::max(1, ctx->cfg.hist_bins);
+    HIPCHK(hipMemsetAsync(D.acc, 0, kAccLen * sizeof(double), ctx->stream));
+    HIPCHK(hipMemsetAsync(D.rho, 0, D.nc * sizeof(double), ctx->stream));
+    HIPCHK(hipMemsetAsync(D.hist, 0, (size_t)hb * kMaxSpecies * sizeof(int64_t), ctx->stream));
+    StepConst<R> C = step_const<R>(ctx);
+    const int i0 = ctx->box_item_off[box], i1 = ctx->box_item_off[box + 1];
+    HIPCHK(launch_diag<R>(boxes, box, D.nc, ctx->L.items_box + i0, i1 - i0, C, ctx->stream));
+    double acc[kAccLen];
+    HIPCHK(hipMemcpyAsync(acc, D.acc, sizeof(acc), hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<int64_t> hh((size_t)hb * kMaxSpecies);
+    HIPCHK(hipMemcpyAsync(hh.data(), D.hist, hh.size() * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    int32_t novf[kMaxSpecies] = {0, 0, 0, 0};
+    for (int s = 0; s < nsp; ++s)
+        HIPCHK(hipMemcpyAsync(&novf[s], D.sp[s].cnt[ctx->cur] + D.ntiles, sizeof(int32_t), hipMemcpyDeviceToHost,
+                              ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    memset(o, 0, sizeof(*o));
+    o->t = ctx->step * ctx->cfg.dt;
+    o->step = ctx->step;
+    for (int c = 0; c < 3; ++c) {
+        o->W_E[c] = acc[kAccField + c] / D.alpha0;
+        o->W_B[c] = acc[kAccField + 3 + c] / D.alpha0;
+    }
+    o->gauss_max = acc[kAccField + 6];
+    o->gauss_rms = std::sqrt(acc[kAccField + 7] / (double)D.nc);
+    for (int s = 0; s < nsp; ++s) {
+        const double *a = acc + kAccSp + 6 * s;
+        o->K[s] = a[0];
+        o->P[s][0] = a[1]; o->P[s][1] = a[2]; o->P[s][2] = a[3];
+        o->n_particles[s] = (int64_t)std::llround(a[4]);
+        o->sum_gm1[s] = a[5];
+        o->n_overflow[s] = std::min(novf[s], D.sp[s].ovf_cap);
+    }
+    if (hist && ctx->cfg.hist_bins > 0)
+        for (int s = 0; s < nsp; ++s)
+            memcpy(hist + (size_t)s * ctx->cfg.hist_bins, hh.data() + (size_t)s * ctx->cfg.hist_bins,
+                   ctx->cfg.hist_bins * sizeof(int64_t));
+    uint32_t f = 0;
+    int rc = read_flags(ctx, &f);
+    if (rc) return rc;
+    o->flags = f;
+    if (f) {
+        ctx->err = "device error flag raised: " + std::to_string(f);
+        return PIC_EFLAG;
+    }
+    return PIC_OK;
+}
+
+int pic_diag(pic_ctx *ctx, int box, pic_diag_out *out, int64_t *hist)
+{
+    int rc = check_box(ctx, box);
+    if (rc) return rc;
+    if (!out) return PIC_EINVAL;
+    rc = merge(ctx);
+    if (rc) return rc;
+    return ctx->fp64 ? diag_t<double>(ctx, box, out, hist) : diag_t<float>(ctx, box, out, hist);
+}
+
+template <typename R>
+static int get_particles_t(pic_ctx *ctx, int box, int s, double *x, double *u, int32_t *id, int64_t *n)
+{
+    const BoxDev<R> &D = bdvec<R>(ctx)[box];
+    const SpeciesDev<R> &S = D.sp[s];
+    const int nt = D.ntiles;
+    std::vector<int32_t> start(nt + 1), cap(nt + 1), cnt(nt + 1);
+    HIPCHK(hipMemcpyAsync(start.data(), S.seg_start[ctx->cur], (nt + 1) * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(cap.data(), S.seg_cap[ctx->cur], (nt + 1) * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(cnt.data(), S.cnt[ctx->cur], (nt + 1) * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    int64_t total = 0;
+    for (int t = 0; t <= nt; ++t) total += std::min(cnt[t], cap[t]);
+    if (*n < total) {
+        *n = total;
+        ctx->err = "output arrays too small";
+        return PIC_ENOMEM;
+    }
+    const size_t ns = S.slots;
+    std::vector<int32_t> cell(ns), pid(S.buf[ctx->cur].id ? ns : 0);
+    std::vector<R> dd[3], uu[3];
+    const PBuf<R> &P = S.buf[ctx->cur];
+    HIPCHK(hipMemcpyAsync(cell.data(), P.cell, ns * 4, hipMemcpyDeviceToHost, ctx->stream));
+    for (int a = 0; a < 3; ++a) {
+        dd[a].resize(ns);
+        uu[a].resize(ns);
+        HIPCHK(hipMemcpyAsync(dd[a].data(), P.d[a], ns * sizeof(R), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(uu[a].data(), P.u[a], ns * sizeof(R), hipMemcpyDeviceToHost, ctx->stream));
+    }
+    if (P.id) HIPCHK(hipMemcpyAsync(pid.data(), P.id, ns * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::vector<int64_t> order;
+    order.reserve(total);
+    for (int t = 0; t <= nt; ++t)
+        for (int k = 0; k < std::min(cnt[t], cap[t]); ++k) order.push_back(start[t] + k);
+    if (P.id) std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return pid[a] < pid[b]; });
+    for (int64_t q = 0; q < total; ++q) {
+        const int64_t k = order[q];
+        const int c[3] = {cell_x(cell[k]), cell_y(cell[k]), cell_z(cell[k])};
+        for (int a = 0; a < 3; ++a) {
+            if (x) x[3 * q + a] = (double)c[a] + (double)dd[a][k];
+            if (u) u[3 * q + a] = (double)uu[a][k];
+        }
+        if (id) id[q] = P.id ? pid[k] : 0;
+    }
+    *n = total;
+    return PIC_OK;
+}
+
+int pic_get_particles(pic_ctx *ctx, int box, int species, double *x, double *u, int32_t *id, int64_t *n)
+{
+    int rc = check_box(ctx, box);
+    if (rc) return rc;
+    if (species < 0 || species >= ctx->cfg.n_species || !n) return PIC_EINVAL;
+    rc = merge(ctx);
+    if (rc) return rc;
+    return ctx->fp64 ? get_particles_t<double>(ctx, box, species, x, u, id, n)
+                     : get_particles_t<float>(ctx, box, species, x, u, id, n);
+}
+
+template <typename R>
+static int set_particles_t(pic_ctx *ctx, int box, int s, const double *x, const double *u, const int32_t *id,
+                           int64_t n)
+{
+    const BoxDev<R> &D = bdvec<R>(ctx)[box];
+    const SpeciesDev<R> &S = D.sp[s];
+    if (n > ctx->bh[box].stage_cap[s]) { ctx->err = "more particles than the species capacity"; return PIC_ENOMEM; }
+    // drop the binned particles of (box, s): clear the counters of the current copy
+    HIPCHK(hipMemsetAsync(S.cnt[ctx->cur], 0, (D.ntiles + 1) * sizeof(int32_t), ctx->stream));
+    std::vector<int32_t> cell(n), pid(S.stage.id ? n : 0);
+    std::vector<R> dd[3], uu[3];
+    for (int a = 0; a < 3; ++a) { dd[a].resize(n); uu[a].resize(n); }
+    for (int64_t p = 0; p < n; ++p) {
+        int c[3];
+        for (int a = 0; a < 3; ++a) {
+            const int N = D.n[a];
+            double v = std::fmod(x[3 * p + a], (double)N);
+            if (v < 0) v += N;
+            if (v >= N) v -= N;
+            const double f = std::floor(v);
+            R off = (R)(v - f);
+            int ci = (int)f;
+            if (off >= R(1)) { off = R(0); ci += 1; }
+            if (ci >= N) ci -= N;
+            c[a] = ci;
+            dd[a][p] = off;
+            uu[a][p] = (R)u[3 * p + a];
+        }
+        cell[p] = pack_cell(c[0], c[1], c[2]);
+        if (S.stage.id) pid[p] = id ? id[p] : (int32_t)p;
+    }
+    if (n > 0) {
+        HIPCHK(hipMemcpyAsync(S.stage.cell, cell.data(), n * 4, hipMemcpyHostToDevice, ctx->stream));
+        for (int a = 0; a < 3; ++a) {
+            HIPCHK(hipMemcpyAsync(S.stage.d[a], dd[a].data(), n * sizeof(R), hipMemcpyHostToDevice, ctx->stream));
+            HIPCHK(hipMemcpyAsync(S.stage.u[a], uu[a].data(), n * sizeof(R), hipMemcpyHostToDevice, ctx->stream));
+        }
+        if (S.stage.id) HIPCHK(hipMemcpyAsync(S.stage.id, pid.data(), n * 4, hipMemcpyHostToDevice, ctx->stream));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->stage_n[box][s] = (int32_t)n;
+    ctx->stage_half[box][s] = 0;
+    ctx->next_id[box][s] = (int32_t)n;
+    ctx->pending = true;
+    return PIC_OK;
+}
+
+int pic_set_particles(pic_ctx *ctx, int box, int species, const double *x, const double *u, const int32_t *id,
+                      int64_t n)
+{
+    int rc = check_box(ctx, box);
+    if (rc) return rc;
+    if (species < 0 || species >= ctx->cfg.n_species || n < 0 || (n > 0 && (!x || !u))) return PIC_EINVAL;
+    // other pending loads are binned first so that the flags of a stage stay uniform
+    if (ctx->pending) {
+        rc = merge(ctx);
+        if (rc) return rc;
+    }
+    return ctx->fp64 ? set_particles_t<double>(ctx, box, species, x, u, id, n)
+                     : set_particles_t<float>(ctx, box, species, x, u, id, n);
+}
+
+template <typename R>
+static int get_fields_t(pic_ctx *ctx, int box, double *e, double *b, double *j)
+{
+    using JT = typename JType<R>::T;
+    const BoxDev<R> &D = bdvec<R>(ctx)[box];
+    const size_t n3 = 3 * D.nc;
+    std::vector<R> tmp(n3);
+    if (e) {
+        HIPCHK(hipMemcpyAsync(tmp.data(), D.e, n3 * sizeof(R), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        for (size_t q = 0; q < n3; ++q) e[q] = (double)tmp[q];
+    }
+    if (b) {
+        HIPCHK(hipMemcpyAsync(tmp.data(), D.b, n3 * sizeof(R), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        for (size_t q = 0; q < n3; ++q) b[q] = (double)tmp[q];
+    }
+    if (j) {
+        std::vector<JT> jt(n3);
+        HIPCHK(hipMemcpyAsync(jt.data(), D.J, n3 * sizeof(JT), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        const double sc = ctx->fp64 ? 1.0 : std::ldexp(1.0, -kQBits);
+        for (size_t q = 0; q < n3; ++q) j[q] = (double)jt[q] * sc;
+    }
+    return PIC_OK;
+}
+
+int pic_get_fields(pic_ctx *ctx, int box, double *e, double *b, double *j)
+{
+    int rc = check_box(ctx, box);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ctx->fp64 ? get_fields_t<double>(ctx, box, e, b, j) : get_fields_t<float>(ctx, box, e, b, j);
+}
+
+template <typename R>
+static int set_fields_t(pic_ctx *ctx, int box, const double *e, const double *b)
+{
+    const BoxDev<R> &D = bdvec<R>(ctx)[box];
+    const size_t n3 = 3 * D.nc;
+    std::vector<R> tmp(n3);
+    if (e) {
+        for (size_t q = 0; q < n3; ++q) tmp[q] = (R)e[q];
+        HIPCHK(hipMemcpyAsync(D.e, tmp.data(), n3 * sizeof(R), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    if (b) {
+        for (size_t q = 0; q < n3; ++q) tmp[q] = (R)b[q];
+        HIPCHK(hipMemcpyAsync(D.b, tmp.data(), n3 * sizeof(R), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    return PIC_OK;
+}
+
+int pic_set_fields(pic_ctx *ctx, int box, const double *e, const double *b)
+{
+    int rc = check_box(ctx, box);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ctx->fp64 ? set_fields_t<double>(ctx, box, e, b) : set_fields_t<float>(ctx, box, e, b);
+}
+
+template <typename R>
+static int load_t(pic_ctx *ctx, const pic_load_desc *d)
+{
+    const int box = d->box;
+    const BoxHost &H = ctx->bh[box];
+    const BoxDev<R> *boxes = reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes);
+    int64_t npairs;
+    if (d->profile == PIC_PROFILE_UNIFORM) {
+        npairs = std::llround(d->ppc * (double)H.nc);
+    } else {
+        const double cross = (double)H.nc / H.cfg.n[d->profile_axis];
+        npairs = std::llround(d->ppc * cross * 2.0 * d->thickness * std::tanh(d->half_width / d->thickness));
+    }
+    const int sa = d->species_a, sb = d->species_b;
+    const int64_t need_a = ctx->stage_n[box][sa] + npairs + (sa == sb ? npairs : 0);
+    const int64_t need_b = ctx->stage_n[box][sb] + npairs;
+    if (need_a > H.stage_cap[sa] || need_b > H.stage_cap[sb]) {
+        ctx->err = "load exceeds the species capacity";
+        return PIC_ENOMEM;
+    }
+    if (npairs == 0) return PIC_OK;
+    const pic_mj *pops[2] = {&d->mj_a, &d->mj_b};
+    for (int q = 0; q < 2; ++q)
+        HIPCHK(launch_mj_table(pops[q]->theta, pops[q]->gamma_beta, ctx->L.mj_cum, kTabM, kTabN, ctx->L.mj_tab[q],
+                               ctx->stream));
+    LoadArgs L;
+    memset(&L, 0, sizeof(L));
+    L.box = box;
+    L.sa = sa;
+    L.sb = sb;
+    L.npairs = npairs;
+    L.offa = ctx->stage_n[box][sa];
+    L.offb = ctx->stage_n[box][sb] + (sa == sb ? (int32_t)npairs : 0);
+    L.ida = ctx->next_id[box][sa];
+    L.idb = ctx->next_id[box][sb] + (sa == sb ? (int32_t)npairs : 0);
+    L.profile = d->profile;
+    L.paxis = d->profile_axis;
+    L.centre = d->centre;
+    L.thick = d->thickness;
+    L.halfw = d->half_width;
+    L.seed = d->seed;
+    L.stream = d->stream;
+    L.N = kTabN;
+    for (int q = 0; q < 2; ++q) {
+        MJPop &P = q == 0 ? L.A : L.B;
+        P.mu = 1.0 / pops[q]->theta;
+        P.G = std::sqrt(1.0 + pops[q]->gamma_beta * pops[q]->gamma_beta);
+        P.beta0 = pops[q]->gamma_beta / P.G;
+        P.axis = pops[q]->axis;
+        P.tab = ctx->L.mj_tab[q];
+    }
+    HIPCHK(launch_load_pairs<R>(boxes, L, ctx->stream));
+    ctx->stage_n[box][sa] = (int32_t)(L.offa + npairs);
+    ctx->stage_n[box][sb] = (int32_t)(L.offb + npairs);
+    ctx->next_id[box][sa] = (int32_t)(L.ida + npairs);
+    ctx->next_id[box][sb] = (int32_t)(L.idb + npairs);
+    ctx->stage_half[box][sa] = 1;
+    ctx->stage_half[box][sb] = 1;
+    ctx->pending = true;
+    return PIC_OK;
+}
+
+int pic_load_maxwell_juttner(pic_ctx *ctx, const pic_load_desc *d)
+{
+    if (!ctx || !d) return PIC_EINVAL;
+    int rc = check_box(ctx, d->box);
+    if (rc) return rc;
+    const int nsp = ctx->cfg.n_species;
+    if (d->species_a < 0 || d->species_a >= nsp || d->species_b < 0 || d->species_b >= nsp) {
+        ctx->err = "species index out of range";
+        return PIC_EINVAL;
+    }
+    const pic_mj *pops[2] = {&d->mj_a, &d->mj_b};
+    for (auto *p : pops)
+        if (!(p->theta > 0) || p->axis < 0 || p->axis > 2 || !std::isfinite(p->gamma_beta)) {
+            ctx->err = "bad Maxwell-Juttner parameters";
+            return PIC_EINVAL;
+        }
+    if (!(d->ppc >= 0) || (d->profile != PIC_PROFILE_UNIFORM && d->profile != PIC_PROFILE_HARRIS)) {
+        ctx->err = "bad density profile";
+        return PIC_EINVAL;
+    }
+    if (d->profile == PIC_PROFILE_HARRIS &&
+        (d->profile_axis < 0 || d->profile_axis > 2 || !(d->thickness > 0) || !(d->half_width > 0))) {
+        ctx->err = "bad Harris profile";
+        return PIC_EINVAL;
+    }
+    // a stage holds one kind of batch: bin set_particles batches first
+    if (ctx->stage_n[d->box][d->species_a] && !ctx->stage_half[d->box][d->species_a]) merge(ctx);
+    if (ctx->stage_n[d->box][d->species_b] && !ctx->stage_half[d->box][d->species_b]) merge(ctx);
+    return ctx->fp64 ? load_t<double>(ctx, d) : load_t<float>(ctx, d);
+}
+
+int pic_set_harris_field(pic_ctx *ctx, const pic_harris_field *h)
+{
+    if (!ctx || !h) return PIC_EINVAL;
+    int rc = check_box(ctx, h->box);
+    if (rc) return rc;
+    if (h->grad_axis < 0 || h->grad_axis > 2 || h->field_axis < 0 || h->field_axis > 2 ||
+        h->grad_axis == h->field_axis || !(h->thickness > 0) || (h->n_sheets != 1 && h->n_sheets != 2)) {
+        ctx->err = "bad Harris field";
+        return PIC_EINVAL;
+    }
+    const int c0 = ctx->box_cblock_off[h->box], c1 = ctx->box_cblock_off[h->box + 1];
+    if (ctx->fp64) {
+        const BoxDev<double> *boxes = reinterpret_cast<const BoxDev<double> *>(ctx->L.boxes);
+        HIPCHK(launch_harris_field<double>(boxes, ctx->bh[h->box].nc, *h, ctx->stream));
+        HIPCHK(launch_advance_b<double>(boxes, ctx->L.cblocks + c0, c1 - c0, -0.5 * ctx->cfg.dt, ctx->stream));
+    } else {
+        const BoxDev<float> *boxes = reinterpret_cast<const BoxDev<float> *>(ctx->L.boxes);
+        HIPCHK(launch_harris_field<float>(boxes, ctx->bh[h->box].nc, *h, ctx->stream));
+        HIPCHK(launch_advance_b<float>(boxes, ctx->L.cblocks + c0, c1 - c0, (float)(-0.5 * ctx->cfg.dt), ctx->stream));
+    }
+    return PIC_OK;
+}
+
+
+int pic_set_timing(pic_ctx *ctx, int enable)
+{
+    if (!ctx) return PIC_EINVAL;
+    ctx->timing = enable != 0;
+    return PIC_OK;
+}
+
+int pic_get_timing(pic_ctx *ctx, pic_timing *out, int reset)
+{
+    if (!ctx || !out) return PIC_EINVAL;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    int64_t n[3] = {0, 0, 0};
+    double ms[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k)
+        for (auto &p : ctx->ev[k]) {
+            if (!p.second) continue;
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, p.first, p.second));
+            ms[k] += t;
+            n[k] += 1;
+        }
+    out->push_launches = n[0];
+    out->push_ms = ms[0];
+    out->field_launches = n[1];
+    out->field_ms = ms[1];
+    out->sort_launches = n[2];
+    out->sort_ms = ms[2];
+    if (reset)
+        for (auto &v : ctx->ev) {
+            for (auto &p : v) {
+                ctx->ev_pool.push_back(p.first);
+                if (p.second) ctx->ev_pool.push_back(p.second);
+            }
+            v.clear();
+        }
+    return PIC_OK;
+}

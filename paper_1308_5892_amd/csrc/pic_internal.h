@@ -1,0 +1,172 @@
+// Internal device-side layout of the gfx950 PIC library (not part of the ABI).
+//
+// Particles of one (box, species) live in SoA arrays binned by spatial tile:
+// tile T owns the slots [seg_start[c][T], seg_start[c][T] + seg_cap[c][T]) of
+// copy c and holds
+// cnt[cur][T] particles, all with their cell inside T.  The last segment
+// (index ntiles) is an overflow region that takes particles whose tile
+// segment is full; it is swept by the slow path (fields read from HBM,
+// current added with global atomics).  Two copies of the arrays alternate
+// between steps: the push reads copy `cur` and writes each particle straight
+// into the segment of its new tile in copy `cur ^ 1`, so the tile binning is
+// refreshed every step at no extra traffic.  A counting-sort repack
+// recomputes the segment layout from the actual counts.
+//
+// Stored particle state: cell packed as ix | iy << 11 | iz << 22, in-cell
+// offset d in [0, 1) per axis, and u = gamma v / c.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pic.h"
+
+namespace pic {
+
+constexpr int kMaxSpecies = PIC_MAX_SPECIES;
+constexpr int kOvfBlocks = 4;      // blocks per box sweeping the overflow region
+constexpr int kBlock = 256;        // threads per block of the particle kernels
+constexpr int kQBits = 31;         // fractional bits of the fixed-point current
+
+__host__ __device__ inline int32_t pack_cell(int ix, int iy, int iz)
+{
+    return (int32_t)((uint32_t)ix | ((uint32_t)iy << 11) | ((uint32_t)iz << 22));
+}
+__host__ __device__ inline int cell_x(int32_t c) { return (int)((uint32_t)c & 2047u); }
+__host__ __device__ inline int cell_y(int32_t c) { return (int)(((uint32_t)c >> 11) & 2047u); }
+__host__ __device__ inline int cell_z(int32_t c) { return (int)((uint32_t)c >> 22); }
+
+template <typename R>
+struct PBuf {                      // one copy of the particle arrays
+    int32_t *cell;
+    R *d[3];
+    R *u[3];
+    int32_t *id;                   // nullptr without PIC_TRACK_IDS
+};
+
+template <typename R>
+struct SpeciesDev {
+    PBuf<R> buf[2];
+    PBuf<R> stage;                 // freshly loaded / set particles, unbinned
+    int32_t *seg_start[2];         // ntiles + 1 per copy (last: overflow region)
+    int32_t *seg_cap[2];           // ntiles + 1 per copy
+    int32_t *cnt[2];               // ntiles + 1 counters per copy
+    int32_t *tcount;               // ntiles + 1, repack scratch
+    int32_t slots;                 // length of each array
+    int32_t ovf_cap;               // slots reserved for the overflow region
+};
+
+// J type: int64 fixed point (2^-31 cell volumes) for FP32, double for FP64.
+template <typename R> struct JType;
+template <> struct JType<float> { using T = long long; };
+template <> struct JType<double> { using T = double; };
+
+template <typename R>
+struct BoxDev {
+    int32_t n[3];
+    int32_t tshift[3];             // log2 of the tile edge per axis
+    int32_t ntile[3];
+    int32_t ntiles;
+    int64_t nc;
+    R *e;                          // 3 * nc, e^t
+    R *b;                          // 3 * nc, b^{t-dt/2}
+    typename JType<R>::T *J;       // 3 * nc, current of the step in flight
+    double *rho;                   // nc, diagnostic charge density
+    double *acc;                   // diagnostic accumulators (kAccLen doubles)
+    int64_t *hist;                 // n_species * hist_bins
+    double alpha0;                 // 2 / (n_x^2 rho0)
+    SpeciesDev<R> sp[kMaxSpecies];
+};
+
+// per-launch constants of the particle kernels
+template <typename R>
+struct StepConst {
+    R dt;
+    int32_t nsp;
+    R kq[kMaxSpecies];             // (q/e)(m_e/m)
+    R qs[kMaxSpecies];             // sgn(q)
+    R mass[kMaxSpecies];           // m/m_e
+    uint32_t *flags;               // device error flag word
+    int32_t cur;                   // copy read this step
+    int32_t hist_bins;
+    double hist_lo, hist_hi;
+};
+
+// diagnostic accumulator layout per box
+constexpr int kAccField = 0;       // [0..2] sum e^2/2, [3..5] sum (b^t)^2/2, [6] gauss max, [7] gauss sum sq
+constexpr int kAccSp = 8;          // then per species 6: K, P[3], count, sum(gamma-1)
+constexpr int kAccLen = kAccSp + 6 * kMaxSpecies;
+
+// work item of the particle kernels: box, and tile (>= 0) or -1-k for overflow block k
+struct Item {
+    int32_t box;
+    int32_t tile;
+};
+
+__device__ inline int wrap_idx(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+template <typename R>
+__device__ inline int tile_of(const BoxDev<R> &B, int32_t c)
+{
+    return (cell_x(c) >> B.tshift[0]) +
+           B.ntile[0] * ((cell_y(c) >> B.tshift[1]) + B.ntile[1] * (cell_z(c) >> B.tshift[2]));
+}
+
+// cell blocks of the field kernels: (box, first cell) of kBlock cells
+struct CellBlock {
+    int32_t box;
+    int32_t first;
+};
+
+// stage item: particles [first, last) of the stage of (box, species); half:
+// integrate their momenta back by dt/2 when they are binned
+struct StageItem {
+    int32_t box, species, first, last, half;
+};
+
+// one drifting Maxwell-Juttner population of a load
+struct MJPop {
+    double mu, G, beta0;
+    int axis;
+    const double *tab;
+};
+
+struct LoadArgs {
+    int32_t box, sa, sb;
+    int64_t npairs;
+    int32_t offa, offb;        // first stage slot of each species
+    int32_t ida, idb;          // first particle id of each species
+    int32_t profile, paxis;
+    double centre, thick, halfw;
+    uint64_t seed, stream;
+    int N;                     // table intervals
+    MJPop A, B;
+};
+
+// launchers (pic_kernels.hip, pic_loader.hip)
+template <typename R> size_t push_lds_bytes(int t0, int t1, int t2);
+template <typename R>
+hipError_t launch_push(const BoxDev<R> *boxes, const Item *items, int nitems, size_t lds, const StepConst<R> &C,
+                       hipStream_t st);
+template <typename R>
+hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R dt, int nsp,
+                         int clear_copy, hipStream_t st);
+template <typename R>
+hipError_t launch_advance_b(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R h, hipStream_t st);
+template <typename R>
+hipError_t launch_repack(const BoxDev<R> *boxes, int nboxes, const Item *items, int nitems,
+                         const StageItem *sitems, int nsitems, const StepConst<R> &C, hipStream_t st);
+template <typename R>
+hipError_t launch_diag(const BoxDev<R> *boxes, int box, int64_t nc, const Item *items, int nitems,
+                       const StepConst<R> &C, hipStream_t st);
+hipError_t launch_mj_table(double theta, double gamma_beta, double *cum, int M, int N, double *tab,
+                           hipStream_t st);
+template <typename R> hipError_t launch_load_pairs(const BoxDev<R> *boxes, const LoadArgs &L, hipStream_t st);
+template <typename R>
+hipError_t launch_harris_field(const BoxDev<R> *boxes, int64_t nc, const pic_harris_field &H, hipStream_t st);
+
+} // namespace pic

@@ -1,0 +1,140 @@
+"""Host-side checks of the C ABI (no GPU needed): libpic.so loads and exports
+every function include/pic.h declares, the ctypes structures match the C
+layout, and the host-only validation paths (pic_plan, the stability checks of
+pic_init) behave as documented."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pic.h")
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1308_5892_amd import pic
+    if not os.path.exists(pic.LIB_PATH):
+        from paper_1308_5892_amd import build
+        build.build()
+    pic.lib()
+    return pic
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char \*)\s*(pic_\w+)\s*\(", txt, re.M)))
+
+
+def test_every_declared_symbol_is_exported(P):
+    names = _declared()
+    assert len(names) >= 14
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\sT\s(pic_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    assert sorted(P.EXPORTED) == names
+
+
+def test_struct_layout_matches_header(P, tmp_path):
+    structs = {
+        "pic_species": P.pic_species, "pic_box": P.pic_box, "pic_config": P.pic_config,
+        "pic_mj": P.pic_mj, "pic_load_desc": P.pic_load_desc,
+        "pic_harris_field": P.pic_harris_field, "pic_diag_out": P.pic_diag_out,
+        "pic_timing": P.pic_timing,
+    }
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "pic.h"', "int main(void){"]
+    for name, cls in structs.items():
+        src.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            src.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    src.append("return 0;}")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == C.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+
+
+def _cfg(P, **kw):
+    box = {"n": (16, 16, 16), "n_x": 10.0, "rho0": 16.0, "max_particles": [32768, 32768]}
+    box.update(kw.pop("box", {}))
+    return P.make_config([box], [(-1.0, 1.0), (1.0, 1.0)], kw.pop("dt", 0.5), **kw)
+
+
+def test_plan_sizes(P):
+    a = P.pic_plan(_cfg(P))
+    b = P.pic_plan(_cfg(P, box={"max_particles": [65536, 65536]}))
+    c = P.pic_plan(_cfg(P, fp64=True))
+    d = P.pic_plan(_cfg(P, track_ids=True))
+    assert 0 < a < b
+    assert c > a and d > a
+    # fields (e, b: 3 FP32 each; J: 3 int64) and two particle copies of 28 B at least
+    assert a > 16 ** 3 * (24 + 24) + 2 * 2 * 32768 * 28
+
+
+@pytest.mark.parametrize("bad", [
+    {"box": {"n": (0, 16, 16)}},
+    {"box": {"n": (4096, 4, 4)}},
+    {"box": {"tile": (3, 4, 4)}},
+    {"box": {"tile": (16, 4, 4)}},
+    {"box": {"n_x": 0.0}},
+    {"dt": -0.1},
+    {"headroom": 1.01},
+    {"hist_bins": 8, "hist_lo": 1.0, "hist_hi": 0.0},
+])
+def test_plan_rejects_bad_config(P, bad):
+    with pytest.raises(P.PicError) as ei:
+        P.pic_plan(_cfg(P, **bad))
+    assert ei.value.code == P.PIC_EINVAL
+
+
+def test_plan_rejects_bad_species(P):
+    cfg = P.make_config([{"n": (8, 8, 8), "n_x": 10.0, "rho0": 2.0, "max_particles": [10]}],
+                        [(-0.5, 1.0)], 0.5)
+    with pytest.raises(P.PicError):
+        P.pic_plan(cfg)
+
+
+def test_init_refuses_courant_violation_before_touching_the_device(P):
+    # 3-D Yee needs dt < 1/sqrt(3); 0.6 passes the printed 2-D bound 1/sqrt(2) but not this one
+    ctx = C.c_void_p()
+    cfg = _cfg(P, dt=0.6)
+    rc = P.lib().pic_init(C.byref(cfg), C.c_void_p(256), 1 << 40, None, C.byref(ctx))
+    assert rc == P.PIC_ECOURANT
+    # omega_pe dt = dt / n_x must stay below 2 (electric part of the mover)
+    cfg = _cfg(P, dt=0.5, box={"n_x": 0.2})
+    rc = P.lib().pic_init(C.byref(cfg), C.c_void_p(256), 1 << 40, None, C.byref(ctx))
+    assert rc == P.PIC_ECOURANT
+
+
+def test_init_refuses_small_or_misaligned_arena(P):
+    ctx = C.c_void_p()
+    cfg = _cfg(P)
+    need = P.pic_plan(cfg)
+    assert P.lib().pic_init(C.byref(cfg), C.c_void_p(256), need - 1, None, C.byref(ctx)) == P.PIC_ENOMEM
+    assert P.lib().pic_init(C.byref(cfg), C.c_void_p(0), need, None, C.byref(ctx)) == P.PIC_ENOMEM
+    assert P.lib().pic_init(C.byref(cfg), C.c_void_p(264), need, None, C.byref(ctx)) == P.PIC_EINVAL
+
+
+def test_null_context_calls_are_rejected(P):
+    L = P.lib()
+    assert L.pic_step(None, 1) == P.PIC_EINVAL
+    assert L.pic_sync(None) == P.PIC_EINVAL
+    assert L.pic_free(None) == P.PIC_EINVAL
+    assert L.pic_steps_done(None) == -1
+
+
+def test_product_package_does_not_reference_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1308_5892_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in txt.lower(), f

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#define PIC_HOST_ONLY_TU   // no kernels here: descriptor pointers stay generic
 #include "pic_internal.h"
 
 namespace pic {
@@ -89,8 +90,11 @@ static void carve(Bump &A, const pic_config *cfg, std::vector<BoxHost> &bh, std:
                 S.seg_start[c] = A.take<int32_t>(H.ntiles + 1);
                 S.seg_cap[c] = A.take<int32_t>(H.ntiles + 1);
             }
-            S.cnt[0] = A.take<int32_t>(H.ntiles + 1);
-            S.cnt[1] = A.take<int32_t>(H.ntiles + 1);
+            for (int c = 0; c < 2; ++c) {
+                S.na[c] = A.take<int32_t>(H.ntiles + 1);
+                S.nb[c] = A.take<int32_t>(H.ntiles + 1);
+                S.bs[c] = A.take<int32_t>(H.ntiles + 1);
+            }
             S.tcount = A.take<int32_t>(H.ntiles + 1);
             S.slots = H.slots[s];
             S.ovf_cap = H.ovf_cap[s];
@@ -516,7 +520,7 @@ static int diag_t(pic_ctx *ctx, int box, pic_diag_out *o, int64_t *hist)
     HIPCHK(hipMemcpyAsync(hh.data(), D.hist, hh.size() * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
     int32_t novf[kMaxSpecies] = {0, 0, 0, 0};
     for (int s = 0; s < nsp; ++s)
-        HIPCHK(hipMemcpyAsync(&novf[s], D.sp[s].cnt[ctx->cur] + D.ntiles, sizeof(int32_t), hipMemcpyDeviceToHost,
+        HIPCHK(hipMemcpyAsync(&novf[s], D.sp[s].nb[ctx->cur] + D.ntiles, sizeof(int32_t), hipMemcpyDeviceToHost,
                               ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     memset(o, 0, sizeof(*o));
@@ -567,13 +571,23 @@ static int get_particles_t(pic_ctx *ctx, int box, int s, double *x, double *u, i
     const BoxDev<R> &D = bdvec<R>(ctx)[box];
     const SpeciesDev<R> &S = D.sp[s];
     const int nt = D.ntiles;
-    std::vector<int32_t> start(nt + 1), cap(nt + 1), cnt(nt + 1);
+    std::vector<int32_t> start(nt + 1), cap(nt + 1), na(nt + 1), nb(nt + 1), bs(nt + 1);
     HIPCHK(hipMemcpyAsync(start.data(), S.seg_start[ctx->cur], (nt + 1) * 4, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipMemcpyAsync(cap.data(), S.seg_cap[ctx->cur], (nt + 1) * 4, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipMemcpyAsync(cnt.data(), S.cnt[ctx->cur], (nt + 1) * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(na.data(), S.na[ctx->cur], (nt + 1) * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(nb.data(), S.nb[ctx->cur], (nt + 1) * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(bs.data(), S.bs[ctx->cur], (nt + 1) * 4, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    int64_t total = 0;
-    for (int t = 0; t <= nt; ++t) total += std::min(cnt[t], cap[t]);
+    // slots in use: per tile the A range [0, na) and the B range [bs, bs + nb)
+    // (clamped to the segment), then the overflow region
+    std::vector<int64_t> order;
+    for (int t = 0; t < nt; ++t) {
+        for (int k = 0; k < na[t]; ++k) order.push_back(start[t] + k);
+        const int nbv = std::max(0, std::min(nb[t], cap[t] - bs[t]));
+        for (int k = 0; k < nbv; ++k) order.push_back(start[t] + bs[t] + k);
+    }
+    for (int k = 0; k < std::min(nb[nt], cap[nt]); ++k) order.push_back(start[nt] + k);
+    const int64_t total = (int64_t)order.size();
     if (*n < total) {
         *n = total;
         ctx->err = "output arrays too small";
@@ -592,10 +606,6 @@ static int get_particles_t(pic_ctx *ctx, int box, int s, double *x, double *u, i
     }
     if (P.id) HIPCHK(hipMemcpyAsync(pid.data(), P.id, ns * 4, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    std::vector<int64_t> order;
-    order.reserve(total);
-    for (int t = 0; t <= nt; ++t)
-        for (int k = 0; k < std::min(cnt[t], cap[t]); ++k) order.push_back(start[t] + k);
     if (P.id) std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return pid[a] < pid[b]; });
     for (int64_t q = 0; q < total; ++q) {
         const int64_t k = order[q];
@@ -629,7 +639,8 @@ static int set_particles_t(pic_ctx *ctx, int box, int s, const double *x, const 
     const SpeciesDev<R> &S = D.sp[s];
     if (n > ctx->bh[box].stage_cap[s]) { ctx->err = "more particles than the species capacity"; return PIC_ENOMEM; }
     // drop the binned particles of (box, s): clear the counters of the current copy
-    HIPCHK(hipMemsetAsync(S.cnt[ctx->cur], 0, (D.ntiles + 1) * sizeof(int32_t), ctx->stream));
+    HIPCHK(hipMemsetAsync(S.na[ctx->cur], 0, (D.ntiles + 1) * sizeof(int32_t), ctx->stream));
+    HIPCHK(hipMemsetAsync(S.nb[ctx->cur], 0, (D.ntiles + 1) * sizeof(int32_t), ctx->stream));
     std::vector<int32_t> cell(n), pid(S.stage.id ? n : 0);
     std::vector<R> dd[3], uu[3];
     for (int a = 0; a < 3; ++a) { dd[a].resize(n); uu[a].resize(n); }

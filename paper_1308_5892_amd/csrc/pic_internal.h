@@ -1,16 +1,21 @@
 // Internal device-side layout of the gfx950 PIC library (not part of the ABI).
 //
-// Particles of one (box, species) live in SoA arrays binned by spatial tile:
-// tile T owns the slots [seg_start[c][T], seg_start[c][T] + seg_cap[c][T]) of
-// copy c and holds
-// cnt[cur][T] particles, all with their cell inside T.  The last segment
-// (index ntiles) is an overflow region that takes particles whose tile
-// segment is full; it is swept by the slow path (fields read from HBM,
-// current added with global atomics).  Two copies of the arrays alternate
-// between steps: the push reads copy `cur` and writes each particle straight
-// into the segment of its new tile in copy `cur ^ 1`, so the tile binning is
-// refreshed every step at no extra traffic.  A counting-sort repack
-// recomputes the segment layout from the actual counts.
+// Particles of one (box, species) live in SoA arrays binned by spatial tile.
+// Two copies of the arrays alternate between steps: the push reads copy
+// `cur` and writes every particle straight into the segment of its new tile in
+// copy `cur ^ 1`, so the binning is refreshed every step at no extra traffic.
+// Tile T owns the slots [seg_start[c][T], seg_start[c][T] + seg_cap[c][T]) of
+// copy c and holds two ranges of particles there, all with their cell in T:
+//   A = [0, na[c][T])                the tile's own particles that stayed,
+//   B = [bs[c][T], bs[c][T] + nb[c][T])  particles that entered from elsewhere.
+// The block that pushes tile T writes A from the front with an LDS counter and
+// stages its leavers at the back of [0, n_src); at the end it hands them to
+// the neighbouring tiles' B ranges, one global atomic per neighbour.  bs of the
+// next step is the current particle count of the tile, set between steps.
+// The last segment (index ntiles) is an overflow region (count nb[c][ntiles])
+// for particles whose target range is full; it is swept by the slow path
+// (fields read from HBM, current added with global atomics).  A counting-sort
+// repack recomputes the segment layout from the actual counts.
 //
 // Stored particle state: cell packed as ix | iy << 11 | iz << 22, in-cell
 // offset d in [0, 1) per axis, and u = gamma v / c.
@@ -20,6 +25,17 @@
 #include <stdint.h>
 
 #include "pic.h"
+
+// Device pointers into the arena are global-memory pointers; saying so in the
+// descriptor types lets the compiler emit global_* instead of flat_* memory
+// instructions for every access through them.  The qualifier only exists in
+// the device compilation of files with kernels; the host (and the host-only
+// API file, which defines PIC_HOST_ONLY_TU) sees plain pointers of the same size.
+#if defined(__HIP_DEVICE_COMPILE__) && !defined(PIC_HOST_ONLY_TU)
+#define PIC_GLOBAL __attribute__((address_space(1)))
+#else
+#define PIC_GLOBAL
+#endif
 
 namespace pic {
 
@@ -38,20 +54,22 @@ __host__ __device__ inline int cell_z(int32_t c) { return (int)((uint32_t)c >> 2
 
 template <typename R>
 struct PBuf {                      // one copy of the particle arrays
-    int32_t *cell;
-    R *d[3];
-    R *u[3];
-    int32_t *id;                   // nullptr without PIC_TRACK_IDS
+    PIC_GLOBAL int32_t *cell;
+    PIC_GLOBAL R *d[3];
+    PIC_GLOBAL R *u[3];
+    PIC_GLOBAL int32_t *id;        // nullptr without PIC_TRACK_IDS
 };
 
 template <typename R>
 struct SpeciesDev {
     PBuf<R> buf[2];
     PBuf<R> stage;                 // freshly loaded / set particles, unbinned
-    int32_t *seg_start[2];         // ntiles + 1 per copy (last: overflow region)
-    int32_t *seg_cap[2];           // ntiles + 1 per copy
-    int32_t *cnt[2];               // ntiles + 1 counters per copy
-    int32_t *tcount;               // ntiles + 1, repack scratch
+    PIC_GLOBAL int32_t *seg_start[2];   // ntiles + 1 per copy (last: overflow region)
+    PIC_GLOBAL int32_t *seg_cap[2];     // ntiles + 1 per copy
+    PIC_GLOBAL int32_t *na[2];          // ntiles + 1 per copy: A-range count
+    PIC_GLOBAL int32_t *nb[2];          // ntiles + 1 per copy: B-range count (overflow count last)
+    PIC_GLOBAL int32_t *bs[2];          // ntiles + 1 per copy: B-range start
+    PIC_GLOBAL int32_t *tcount;         // ntiles + 1, repack scratch
     int32_t slots;                 // length of each array
     int32_t ovf_cap;               // slots reserved for the overflow region
 };
@@ -68,12 +86,12 @@ struct BoxDev {
     int32_t ntile[3];
     int32_t ntiles;
     int64_t nc;
-    R *e;                          // 3 * nc, e^t
-    R *b;                          // 3 * nc, b^{t-dt/2}
-    typename JType<R>::T *J;       // 3 * nc, current of the step in flight
-    double *rho;                   // nc, diagnostic charge density
-    double *acc;                   // diagnostic accumulators (kAccLen doubles)
-    int64_t *hist;                 // n_species * hist_bins
+    PIC_GLOBAL R *e;               // 3 * nc, e^t
+    PIC_GLOBAL R *b;               // 3 * nc, b^{t-dt/2}
+    PIC_GLOBAL typename JType<R>::T *J;   // 3 * nc, current of the step in flight
+    PIC_GLOBAL double *rho;        // nc, diagnostic charge density
+    PIC_GLOBAL double *acc;        // diagnostic accumulators (kAccLen doubles)
+    PIC_GLOBAL int64_t *hist;      // n_species * hist_bins
     double alpha0;                 // 2 / (n_x^2 rho0)
     SpeciesDev<R> sp[kMaxSpecies];
 };
@@ -86,7 +104,7 @@ struct StepConst {
     R kq[kMaxSpecies];             // (q/e)(m_e/m)
     R qs[kMaxSpecies];             // sgn(q)
     R mass[kMaxSpecies];           // m/m_e
-    uint32_t *flags;               // device error flag word
+    PIC_GLOBAL uint32_t *flags;    // device error flag word
     int32_t cur;                   // copy read this step
     int32_t hist_bins;
     double hist_lo, hist_hi;
@@ -132,7 +150,7 @@ struct StageItem {
 struct MJPop {
     double mu, G, beta0;
     int axis;
-    const double *tab;
+    const PIC_GLOBAL double *tab;
 };
 
 struct LoadArgs {

@@ -23,7 +23,9 @@ template <typename R> __device__ inline R qscale_bits();
 template <> __device__ inline float qscale_bits<float>() { return 2147483648.0f; }  // 2^31
 template <> __device__ inline double qscale_bits<double>() { return 1.0; }
 
-__device__ inline long long quantize(float v) { return (long long)__float2int_rn(v); }
+// FP32 form: a value already scaled by 2^31 rounded to the nearest integer
+// (|value| < 2^31 since every face value of one move is below one cell volume)
+__device__ inline int quantize(float v) { return __float2int_rn(v); }
 __device__ inline double quantize(double v) { return v; }
 
 __device__ inline void atomic_add_lds(long long *p, long long v)
@@ -141,7 +143,7 @@ __device__ inline void deposit_move(const R d[3], const R D[3], R scale, Add &&a
 // ------------------------------------------------------ global-memory reads
 
 template <typename R>
-__device__ inline R fld(const R *F, const BoxDev<R> &B, int c, int i, int j, int k)
+__device__ inline R fld(const PIC_GLOBAL R *F, const BoxDev<R> &B, int c, int i, int j, int k)
 {
     i = wrap_idx(i, B.n[0]);
     j = wrap_idx(j, B.n[1]);
@@ -153,7 +155,7 @@ __device__ inline R fld(const R *F, const BoxDev<R> &B, int c, int i, int j, int
 template <typename R>
 __device__ inline R bt_global(const BoxDev<R> &B, int c, int i, int j, int k, R hdt)
 {
-    const R *e = B.e;
+    const PIC_GLOBAL R *e = B.e;
     R curl;
     if (c == 0)
         curl = (fld(e, B, 2, i, j + 1, k) - fld(e, B, 2, i, j, k)) - (fld(e, B, 1, i, j, k + 1) - fld(e, B, 1, i, j, k));
@@ -195,7 +197,7 @@ __device__ inline uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; 
 
 // Wave-aggregated claim of one slot per pending lane in the counter of its
 // target segment: one atomic per distinct target in the wave.
-__device__ inline int claim_slot(int32_t *cnt, int target, bool pending)
+__device__ inline int claim_slot(PIC_GLOBAL int32_t *cnt, int target, bool pending)
 {
     int slot = -1;
     uint64_t m;
@@ -215,30 +217,71 @@ __device__ inline int claim_slot(int32_t *cnt, int target, bool pending)
     return slot;
 }
 
-// Store a particle into copy `dst` at the segment of tile `tgt` (or overflow).
+template <typename R>
+__device__ inline void write_particle(const PBuf<R> &P, int at, int32_t cell, const R d[3], const R u[3], int32_t id)
+{
+    P.cell[at] = cell;
+    P.d[0][at] = d[0]; P.d[1][at] = d[1]; P.d[2][at] = d[2];
+    P.u[0][at] = u[0]; P.u[1][at] = u[1]; P.u[2][at] = u[2];
+    if (P.id) P.id[at] = id;
+}
+
+// Slot of copy `dst` for position `pos` of the B range of tile `tgt`, or of the
+// overflow region when the segment is full; -1 (and the LOST flag) when both are.
+template <typename R>
+__device__ inline int b_range_slot(const BoxDev<R> &B, const SpeciesDev<R> &S, int dst, int tgt, int pos,
+                                   PIC_GLOBAL uint32_t *flags)
+{
+    if (pos < S.seg_cap[dst][tgt]) return S.seg_start[dst][tgt] + pos;
+    const int o = atomicAdd(&S.nb[dst][B.ntiles], 1);
+    if (o >= S.ovf_cap) {
+        atomicOr(flags, PIC_FLAG_LOST);
+        return -1;
+    }
+    return S.seg_start[dst][B.ntiles] + o;
+}
+
+// Store a particle into the B range of tile `tgt` of copy `dst` (or the
+// overflow region); slots are claimed with one atomic per distinct target in
+// the wave.  Every lane of the wave must call it.
 template <typename R>
 __device__ inline void store_particle(const BoxDev<R> &B, const SpeciesDev<R> &S, int dst, int tgt, bool valid,
-                                      int32_t cell, const R d[3], const R u[3], int32_t id, uint32_t *flags)
+                                      int32_t cell, const R d[3], const R u[3], int32_t id,
+                                      PIC_GLOBAL uint32_t *flags)
 {
-    int32_t *cnt = S.cnt[dst];
-    int slot = claim_slot(cnt, tgt, valid);
+    const int slot = claim_slot(S.nb[dst], tgt, valid);
     if (!valid) return;
-    int idx;
-    if (slot < S.seg_cap[dst][tgt]) {
-        idx = S.seg_start[dst][tgt] + slot;
-    } else {
-        const int o = atomicAdd(&cnt[B.ntiles], 1);
-        if (o >= S.ovf_cap) {
-            atomicOr(flags, PIC_FLAG_LOST);
-            return;
-        }
-        idx = S.seg_start[dst][B.ntiles] + o;
-    }
-    const PBuf<R> &P = S.buf[dst];
-    P.cell[idx] = cell;
-    P.d[0][idx] = d[0]; P.d[1][idx] = d[1]; P.d[2][idx] = d[2];
-    P.u[0][idx] = u[0]; P.u[1][idx] = u[1]; P.u[2][idx] = u[2];
-    if (P.id) P.id[idx] = id;
+    const int at = b_range_slot(B, S, dst, tgt, S.bs[dst][tgt] + slot, flags);
+    if (at >= 0) write_particle(S.buf[dst], at, cell, d, u, id);
+}
+
+// The particles of tile T in copy c: the A range then the clamped B range.
+struct TileRanges {
+    int start, na, bs, n;
+    __device__ int slot(int q) const { return start + (q < na ? q : bs + (q - na)); }
+};
+
+template <typename R>
+__device__ inline TileRanges tile_ranges(const SpeciesDev<R> &S, int c, int T)
+{
+    TileRanges r;
+    r.start = S.seg_start[c][T];
+    r.na = S.na[c][T];
+    r.bs = S.bs[c][T];
+    r.n = r.na + max(0, min(S.nb[c][T], S.seg_cap[c][T] - r.bs));
+    return r;
+}
+
+// The overflow region of copy c as a range.
+template <typename R>
+__device__ inline TileRanges overflow_range(const BoxDev<R> &B, const SpeciesDev<R> &S, int c)
+{
+    TileRanges r;
+    r.start = S.seg_start[c][B.ntiles];
+    r.na = min(S.nb[c][B.ntiles], S.ovf_cap);
+    r.bs = 0;
+    r.n = r.na;
+    return r;
 }
 
 // New cell and offset after the move x1 = d + D (home-cell frame), wrapped.
@@ -289,7 +332,21 @@ __device__ inline TileGeom<R> tile_geom(const BoxDev<R> &B, int T)
     return g;
 }
 
-// Bytes of dynamic LDS for a tile with edges (t0, t1, t2).
+// Per-wave queue of deposit pieces (LDS ring buffer): the pieces of a move
+// after the first one (cell-crossing moves) wait here and are deposited 64 at
+// a time by the whole wave.
+constexpr int kQCap = 128;
+constexpr int kWaves = kBlock / 64;
+
+template <typename R>
+__host__ __device__ inline size_t queue_bytes()
+{
+    return (size_t)kWaves * kQCap * (sizeof(int32_t) + 6 * sizeof(R));
+}
+
+// Bytes of dynamic LDS for a tile with edges (t0, t1, t2): node fields, the
+// piece queues, then a region that first holds the raw staged fields and then
+// the tile current.
 template <typename R>
 __host__ __device__ inline size_t tile_lds_bytes(int t0, int t1, int t2)
 {
@@ -299,7 +356,78 @@ __host__ __device__ inline size_t tile_lds_bytes(int t0, int t1, int t2)
     const size_t raw = 3 * (jn + bn) * sizeof(R);
     const size_t jb = 3 * jn * sizeof(typename JType<R>::T);
     const size_t u = raw > jb ? raw : jb;
-    return nn * 8 * sizeof(R) + ((u + 15) & ~size_t(15));
+    return nn * 8 * sizeof(R) + queue_bytes<R>() + ((u + 15) & ~size_t(15));
+}
+
+// The twelve face values of one piece (App. A.3.4, eq. current_dep), added to
+// the tile current at jl[cb + off[a][f]]: component a, faces (pp, qq) in
+// {(0,0), (0,1), (1,0), (1,1)} along the two other axes b1 = a+1, b2 = a+2.
+// With m = s + dd/2 and K = dd_b1 dd_b2 / 12 the weights are
+// (1-m1)(1-m2)+K, (1-m1)m2-K, m1(1-m2)-K, m1 m2+K; they sum to one, so the
+// (0,0) value is the total minus the other three (taken after rounding to the
+// fixed-point grid in the FP32 form, so each component's four values add up
+// to the rounded total).
+template <typename R>
+__device__ inline void deposit_piece(typename JType<R>::T *jl, int cb, const int (&off)[3][4], const R s[3],
+                                     const R dd[3], R scale)
+{
+    const R m[3] = {s[0] + R(0.5) * dd[0], s[1] + R(0.5) * dd[1], s[2] + R(0.5) * dd[2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int b1 = a == 2 ? 0 : a + 1, b2 = a == 0 ? 2 : a - 1;
+        const R PK = m[b1] * m[b2] + dd[b1] * dd[b2] * R(1.0 / 12.0);
+        const R F = scale * dd[a];
+        const R t11 = F * PK, t01 = F * (m[b2] - PK), t10 = F * (m[b1] - PK);
+        const auto q11 = quantize(t11), q01 = quantize(t01), q10 = quantize(t10);
+        const auto q00 = quantize(F) - q01 - q10 - q11;
+        atomic_add_lds(&jl[cb + off[a][0]], q00);
+        atomic_add_lds(&jl[cb + off[a][1]], q01);
+        atomic_add_lds(&jl[cb + off[a][2]], q10);
+        atomic_add_lds(&jl[cb + off[a][3]], q11);
+    }
+}
+
+template <typename R>
+__device__ inline R sel3(int i, R a0, R a1, R a2) { return i == 0 ? a0 : (i == 1 ? a1 : a2); }
+
+// Tile one step away from tile T in direction code = (dx+1) + 3(dy+1) + 9(dz+1).
+template <typename R>
+__device__ inline int neighbor_tile(const BoxDev<R> &B, const TileGeom<R> &g, int code)
+{
+    int t = 0, mul = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int dl = code % 3 - 1;
+        code /= 3;
+        int ta = (g.o[a] >> B.tshift[a]) + dl;
+        ta = ta < 0 ? ta + B.ntile[a] : (ta >= B.ntile[a] ? ta - B.ntile[a] : ta);
+        t += ta * mul;
+        mul *= B.ntile[a];
+    }
+    return t;
+}
+
+// Direction code of a particle in cell c (tile tn) relative to tile g: 13 if it
+// is inside g, the code of the adjacent tile it sits in, or -1 when neither
+// holds.  A pure function of the stored cell, so that the push and the
+// hand-over of the leavers classify a particle the same way.
+template <typename R>
+__device__ inline int move_bin(const BoxDev<R> &B, const TileGeom<R> &g, int tn, const int c[3])
+{
+    int code = 0, mul = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int rel = c[a] - g.o[a];
+        int dl;
+        if (rel >= 0 && rel < g.ext[a]) dl = 0;
+        else if (c[a] == wrap_idx(g.o[a] - 1, B.n[a])) dl = -1;
+        else if (c[a] == wrap_idx(g.o[a] + g.ext[a], B.n[a])) dl = 1;
+        else return -1;
+        code += (dl + 1) * mul;
+        mul *= 3;
+    }
+    if (code != 13 && neighbor_tile(B, g, code) != tn) return -1;
+    return code;
 }
 
 template <typename R>
@@ -314,8 +442,9 @@ __device__ void push_overflow(const BoxDev<R> &B, int kblk, const StepConst<R> &
     const R hdt = R(0.5) * C.dt;
     for (int s = 0; s < C.nsp; ++s) {
         const SpeciesDev<R> &S = B.sp[s];
-        const int n = min(S.cnt[C.cur][B.ntiles], S.ovf_cap);
-        const int start = S.seg_start[C.cur][B.ntiles];
+        const TileRanges rg = overflow_range(B, S, C.cur);
+        const int n = rg.n;
+        const int start = rg.start;
         const PBuf<R> &P = S.buf[C.cur];
         const R hk = R(0.5) * C.kq[s] * C.dt;
         const R scale = -C.qs[s] * qscale_bits<R>();
@@ -373,14 +502,23 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
     const int tid = threadIdx.x;
     const TileGeom<R> g = tile_geom(B, T);
     R *node = reinterpret_cast<R *>(smem);
-    unsigned char *uni = smem + (((size_t)g.NN * 8 * sizeof(R) + 15) & ~size_t(15));
+    unsigned char *qmem = smem + (((size_t)g.NN * 8 * sizeof(R) + 15) & ~size_t(15));
+    unsigned char *uni = qmem + queue_bytes<R>();
     R *re = reinterpret_cast<R *>(uni);          // raw e, 3 x JN, origin o-1
     R *rb = re + 3 * g.JN;                        // raw b, 3 x BN, origin o-1
     JT *jl = reinterpret_cast<JT *>(uni);         // J, 3 x JN, origin o-1 (after staging)
 
+    // re-binning counters: per species the stayers (from the front of the
+    // tile's new A range), the leavers (staged from the back) and the leavers
+    // per neighbour direction
+    __shared__ int sh_front[kMaxSpecies], sh_back[kMaxSpecies];
+    __shared__ int sh_bin[kMaxSpecies][27], sh_base[kMaxSpecies][27];
+    if (tid < kMaxSpecies) {
+        sh_front[tid] = 0;
+        sh_back[tid] = 0;
+    }
+    if (tid < kMaxSpecies * 27) (&sh_bin[0][0])[tid] = 0;
     int nsp_n[kMaxSpecies];
-    for (int s = 0; s < C.nsp; ++s)
-        nsp_n[s] = min(B.sp[s].cnt[C.cur][T], B.sp[s].seg_cap[C.cur][T]);
 
     // 1. stage e^t and b^{t-dt/2} of the tile and its halo
     const int64_t n0 = B.n[0], n01 = (int64_t)B.n[0] * B.n[1];
@@ -399,8 +537,6 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
         rb[q] = B.b[c * B.nc + gi + n0 * gj + n01 * gk];
     }
     __syncthreads();
-    if (tid == 0)
-        for (int s = 0; s < C.nsp; ++s) B.sp[s].cnt[C.cur][T] = 0;   // read above; reused as output next step
 
     // 2. b^t = b^{t-dt/2} - (dt/2) curl e^t (App. A.3.1 item 1), in place
     const R hdt = R(0.5) * C.dt;
@@ -448,25 +584,81 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
     // 4. particles of every species: gather, push, move, deposit, re-bin
     const int NX = g.NX, NXY = g.NX * g.NY;
     const int JX = g.JX, JXY = g.JX * g.JY;
+    // uniform index offsets of the twelve faces of a piece (see deposit_piece)
+    int joff[3][4];
+    {
+        const int S[3] = {1, JX, JXY};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int b1 = a == 2 ? 0 : a + 1, b2 = a == 0 ? 2 : a - 1;
+            joff[a][0] = a * g.JN;
+            joff[a][1] = a * g.JN + S[b2];
+            joff[a][2] = a * g.JN + S[b1];
+            joff[a][3] = a * g.JN + S[b1] + S[b2];
+        }
+    }
+    // this wave's piece queue: packed cell index (sign bit = species sign), start, displacement
+    const int wave = tid >> 6, lane = __lane_id();
+    int32_t *qidx = reinterpret_cast<int32_t *>(qmem) + wave * kQCap;
+    R *qval = reinterpret_cast<R *>(qmem + kWaves * kQCap * sizeof(int32_t)) + wave * 6 * kQCap;
+    int qhead = 0, qcount = 0;                    // wave-uniform
+    const uint64_t lt = lanemask_lt();
+    auto drain = [&](int limit) {                 // deposit up to `limit` queued pieces (whole wave)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int nq = min(qcount, limit);
+        if (lane < nq) {
+            const int e = (qhead + lane) & (kQCap - 1);
+            const int32_t w = qidx[e];
+            R ps[3], pd[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) { ps[a] = qval[a * kQCap + e]; pd[a] = qval[(3 + a) * kQCap + e]; }
+            const R sc = w < 0 ? -qscale_bits<R>() : qscale_bits<R>();
+            deposit_piece<R>(jl, w & 0x7fffffff, joff, ps, pd, sc);
+        }
+        qhead = (qhead + nq) & (kQCap - 1);
+        qcount -= nq;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
     for (int s = 0; s < C.nsp; ++s) {
         const SpeciesDev<R> &S = B.sp[s];
         const PBuf<R> &P = S.buf[C.cur];
-        const int n = nsp_n[s];
-        const int start = S.seg_start[C.cur][T];
+        const TileRanges src = tile_ranges(S, C.cur, T);
+        const int n = src.n;
+        nsp_n[s] = n;
         const R hk = R(0.5) * C.kq[s] * C.dt;
         const R scale = -C.qs[s] * qscale_bits<R>();
+        const int32_t sgnbit = scale < R(0) ? (int32_t)0x80000000 : 0;
+        const int dst = C.cur ^ 1;
+        const int dst_start = S.seg_start[dst][T];
+        // the particle of the next iteration is loaded one iteration ahead, so
+        // that its HBM latency is covered by the work on the current one
+        const int32_t cell_pad = pack_cell(g.o[0], g.o[1], g.o[2]);
+        int32_t nx_cell = cell_pad, nx_id = 0;
+        R nx_d[3] = {R(0.5), R(0.5), R(0.5)}, nx_u[3] = {R(0), R(0), R(0)};
+        auto fetch = [&](int q) {
+            if (q < n) {
+                const int at = src.slot(q);
+                nx_cell = P.cell[at];
+                nx_d[0] = P.d[0][at]; nx_d[1] = P.d[1][at]; nx_d[2] = P.d[2][at];
+                nx_u[0] = P.u[0][at]; nx_u[1] = P.u[1][at]; nx_u[2] = P.u[2][at];
+                if (P.id) nx_id = P.id[at];
+            } else {
+                nx_cell = cell_pad;
+                nx_d[0] = nx_d[1] = nx_d[2] = R(0.5);
+                nx_u[0] = nx_u[1] = nx_u[2] = R(0);
+            }
+        };
+        fetch(tid);
         for (int pb = 0; pb < n; pb += kBlock) {
             const int p = pb + tid;
             const bool valid = p < n;
-            const int idx = start + (valid ? p : 0);
-            int32_t cell = pack_cell(g.o[0], g.o[1], g.o[2]), id = 0;
-            R d[3] = {R(0.5), R(0.5), R(0.5)}, u[3] = {R(0), R(0), R(0)};
-            if (valid) {
-                cell = P.cell[idx];
-                d[0] = P.d[0][idx]; d[1] = P.d[1][idx]; d[2] = P.d[2][idx];
-                u[0] = P.u[0][idx]; u[1] = P.u[1][idx]; u[2] = P.u[2][idx];
-                if (P.id) id = P.id[idx];
-            }
+            const int32_t cell = nx_cell, id = nx_id;
+            R d[3] = {nx_d[0], nx_d[1], nx_d[2]}, u[3] = {nx_u[0], nx_u[1], nx_u[2]};
+            if (pb + kBlock < n) fetch(p + kBlock);
             const int ix = cell_x(cell), iy = cell_y(cell), iz = cell_z(cell);
             const int lx = ix - g.o[0], ly = iy - g.o[1], lz = iz - g.o[2];
             // every particle of the segment has its cell in the tile; anything
@@ -501,15 +693,97 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
                 u[0] = u[1] = u[2] = R(0);
             }
             const R ig = C.dt * fast_rsqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            R D[3] = {ig * u[0], ig * u[1], ig * u[2]};
-            if (valid && inside) {
-                const int jb = (lx + 1) + JX * (ly + 1) + JXY * (lz + 1);
-                const int JN = g.JN;
-                deposit_move(d, D, scale, [&](int a, int ox, int oy, int oz, R v) {
-                    atomic_add_lds(&jl[a * JN + jb + ox + JX * oy + JXY * oz], quantize(v));
-                });
+            const R D[3] = {ig * u[0], ig * u[1], ig * u[2]};
+
+            // node planes crossed by the move (|D| < 1: at most one per axis),
+            // their crossing parameters in increasing order
+            R x1[3], lam[3];
+            int dir[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                x1[a] = d[a] + D[a];
+                dir[a] = x1[a] < R(0) ? -1 : (x1[a] >= R(1) ? 1 : 0);
+                lam[a] = dir[a] != 0 ? ((dir[a] > 0 ? R(1) : R(0)) - d[a]) * fast_rcp(D[a]) : R(2);
+            }
+            const int nb = (dir[0] != 0) + (dir[1] != 0) + (dir[2] != 0);
+            int o0 = 0, o1 = 1, o2 = 2;
+            R l0 = lam[0], l1 = lam[1], l2 = lam[2];
+            if (l1 < l0) { R t = l0; l0 = l1; l1 = t; int q = o0; o0 = o1; o1 = q; }
+            if (l2 < l1) { R t = l1; l1 = l2; l2 = t; int q = o1; o1 = o2; o2 = q; }
+            if (l1 < l0) { R t = l0; l0 = l1; l1 = t; int q = o0; o0 = o1; o1 = q; }
+            // breakpoint where axis ax (parameter l) meets its plane; the other
+            // coordinates stay on their own side of their planes
+            auto breakpoint = [&](int ax, R l, R q[3]) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    R v = d[a] + l * D[a];
+                    if (dir[a] > 0) v = lam[a] <= l ? fmax(v, R(1)) : fmin(v, R(1));
+                    else if (dir[a] < 0) v = lam[a] <= l ? fmin(v, R(0)) : fmax(v, R(0));
+                    q[a] = a == ax ? (dir[a] > 0 ? R(1) : R(0)) : v;
+                }
+            };
+
+            // new cell and offset, re-binning target, and the slot claims:
+            // the stayers' block of slots by one returning atomic of their
+            // lowest lane, each leaver its own; neither is waited for until
+            // the deposit below is done
+            int cn[3] = {ix, iy, iz};
+            R dn[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                int f = dir[a];
+                R v = x1[a] - R(f);
+                if (v >= R(1)) {        // x1 a hair below 0: rounds onto the cell boundary
+                    v = R(0);
+                    f += 1;
+                }
+                dn[a] = v;
+                int ci = cn[a] + f;
+                ci = ci < 0 ? ci + B.n[a] : (ci >= B.n[a] ? ci - B.n[a] : ci);
+                cn[a] = ci;
+            }
+            const int32_t ncell = pack_cell(cn[0], cn[1], cn[2]);
+            const int tn = tile_of(B, ncell);
+            // re-binning: stayers take the next slots at the front of the
+            // tile's new A range, leavers into an adjacent tile are staged from
+            // the back (both claimed with one LDS atomic per wave); anything
+            // else claims its target's B range with a global atomic
+            const int bin = valid ? move_bin(B, g, tn, cn) : -1;
+            const bool stay = bin == 13, lv = bin >= 0 && bin != 13;
+            const uint64_t ms = __ballot(stay), ml = __ballot(lv);
+            const int sl = ms ? __ffsll((unsigned long long)ms) - 1 : 0;
+            const int ll = ml ? __ffsll((unsigned long long)ml) - 1 : 0;
+            int fb = 0, bb = 0;
+            if (stay && lane == sl) fb = atomicAdd(&sh_front[s], (int)__popcll(ms));
+            if (lv && lane == ll) bb = atomicAdd(&sh_back[s], (int)__popcll(ml));
+            if (lv) atomicAdd(&sh_bin[s][bin], 1);
+            fb = __builtin_amdgcn_readlane(fb, sl);
+            bb = __builtin_amdgcn_readlane(bb, ll);
+            int at = -1;
+            if (stay) {
+                at = dst_start + fb + (int)__popcll(ms & lt);
+            } else if (lv) {
+                at = dst_start + n - 1 - (bb + (int)__popcll(ml & lt));
             } else if (valid) {
-                JT *J = B.J;
+                const int slot = atomicAdd(&S.nb[dst][tn], 1);
+                at = b_range_slot(B, S, dst, tn, S.bs[dst][tn] + slot, C.flags);
+            }
+            if (at >= 0) write_particle(S.buf[dst], at, ncell, dn, u, id);
+
+            // deposit: the first piece (in the home cell) at once, later pieces
+            // through the wave's queue
+            const int jb = (lx + 1) + JX * (ly + 1) + JXY * (lz + 1);
+            R p1[3];
+            if (nb == 0) {
+                p1[0] = x1[0]; p1[1] = x1[1]; p1[2] = x1[2];
+            } else {
+                breakpoint(o0, l0, p1);
+            }
+            if (valid && inside) {
+                const R dd[3] = {p1[0] - d[0], p1[1] - d[1], p1[2] - d[2]};
+                deposit_piece<R>(jl, jb, joff, d, dd, scale);
+            } else if (valid) {
+                PIC_GLOBAL JT *J = B.J;
                 deposit_move(d, D, scale, [&](int a, int ox, int oy, int oz, R v) {
                     const int i = wrap_idx(ix + ox, B.n[0]), j = wrap_idx(iy + oy, B.n[1]),
                               k = wrap_idx(iz + oz, B.n[2]);
@@ -517,12 +791,36 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
                                       quantize(v));
                 });
             }
-            R x1[3] = {d[0] + D[0], d[1] + D[1], d[2] + D[2]}, dn[3];
-            const int32_t nc = advance_cell(B, ix, iy, iz, x1, dn);
-            const int tn = tile_of(B, nc);
-            store_particle(B, S, C.cur ^ 1, tn, valid, nc, dn, u, id, C.flags);
+            R ps[3] = {p1[0], p1[1], p1[2]};
+#pragma unroll
+            for (int k = 1; k <= 3; ++k) {
+                const bool has = valid && inside && k <= nb;
+                const uint64_t mh = __ballot(has);
+                if (mh == 0ull) break;
+                R pe[3];
+                if (k < nb) breakpoint(k == 1 ? o1 : o2, k == 1 ? l1 : l2, pe);
+                else { pe[0] = x1[0]; pe[1] = x1[1]; pe[2] = x1[2]; }
+                if (has) {
+                    const int pos = (qhead + qcount + (int)__popcll(mh & lt)) & (kQCap - 1);
+                    int offc[3];
+                    R sv[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        offc[a] = (int)floor(R(0.5) * (ps[a] + pe[a]));   // cell of the piece
+                        sv[a] = ps[a] - R(offc[a]);
+                        qval[(3 + a) * kQCap + pos] = pe[a] - ps[a];
+                        qval[a * kQCap + pos] = sv[a];
+                    }
+                    qidx[pos] = (jb + offc[0] + JX * offc[1] + JXY * offc[2]) | sgnbit;
+                }
+                qcount += (int)__popcll(mh);
+                ps[0] = pe[0]; ps[1] = pe[1]; ps[2] = pe[2];
+                if (qcount >= 64) drain(64);
+            }
+
         }
     }
+    while (qcount > 0) drain(64);
     __syncthreads();
 
     // 5. flush the tile current to HBM (integer sums: order-independent)
@@ -536,18 +834,71 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
             atomic_add_global(&B.J[c * B.nc + gi + n0 * gj + n01 * gk], v);
         }
     }
+
+    // 6. hand the staged leavers over to the adjacent tiles: one global atomic
+    //    per (species, direction) claims their slots in that tile's B range
+    const int dst = C.cur ^ 1;
+    if (tid < C.nsp * 27) {
+        const int s = tid / 27, k = tid - 27 * s;
+        const int cntk = sh_bin[s][k];
+        if (cntk > 0) sh_base[s][k] = atomicAdd(&B.sp[s].nb[dst][neighbor_tile(B, g, k)], cntk);
+        sh_bin[s][k] = 0;                         // now the rank counter
+    }
+    if (tid < C.nsp) B.sp[tid].na[dst][T] = sh_front[tid];
+    __syncthreads();
+    for (int s = 0; s < C.nsp; ++s) {
+        const SpeciesDev<R> &S = B.sp[s];
+        const PBuf<R> &Q = S.buf[dst];
+        const int nl = sh_back[s];
+        const int first = S.seg_start[dst][T] + nsp_n[s] - nl;   // staged leavers [first, first + nl)
+        for (int q = tid; q < nl; q += kBlock) {
+            const int from = first + q;
+            const int32_t cell = Q.cell[from];
+            const R d[3] = {Q.d[0][from], Q.d[1][from], Q.d[2][from]};
+            const R u[3] = {Q.u[0][from], Q.u[1][from], Q.u[2][from]};
+            const int32_t id = Q.id ? Q.id[from] : 0;
+            const int c3[3] = {cell_x(cell), cell_y(cell), cell_z(cell)};
+            const int tn = tile_of(B, cell);
+            const int k = move_bin(B, g, tn, c3);      // the same bin as at staging
+            const int rank = atomicAdd(&sh_bin[s][k], 1);
+            const int at = b_range_slot(B, S, dst, tn, S.bs[dst][tn] + sh_base[s][k] + rank, C.flags);
+            if (at >= 0) write_particle(Q, at, cell, d, u, id);
+        }
+    }
 }
 
 // ------------------------------------------------------------- Yee updates
 
-// b <- b - h curl e (App. A.3.2)
+// Between two pushes: copy `old` (just read, written by the next push) gets,
+// for tile t, empty A and B ranges with B starting after the particles that
+// the tile now holds in copy old ^ 1, and an empty overflow region.
+template <typename R>
+__device__ inline void next_layout(const BoxDev<R> &B, int nsp, int old, int t)
+{
+    for (int s = 0; s < nsp; ++s) {
+        const SpeciesDev<R> &S = B.sp[s];
+        if (t < B.ntiles) {
+            S.bs[old][t] = tile_ranges(S, old ^ 1, t).n;
+            S.na[old][t] = 0;
+        }
+        S.nb[old][t] = 0;
+    }
+}
+
+// b <- b - h curl e (App. A.3.2); with old >= 0 also prepares the tile
+// descriptors of copy `old` for the next push.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) advance_b_kernel(const BoxDev<R> *__restrict__ boxes,
-                                                           const CellBlock *__restrict__ blocks, R h)
+                                                           const CellBlock *__restrict__ blocks, R h, int nsp,
+                                                           int old)
 {
     const CellBlock cb = blocks[blockIdx.x];
     const BoxDev<R> &B = boxes[cb.box];
     const int64_t p = (int64_t)cb.first + threadIdx.x;
+    if (old >= 0) {
+        if (p < B.ntiles) next_layout(B, nsp, old, (int)p);
+        if (p == 0) next_layout(B, nsp, old, B.ntiles);
+    }
     if (p >= B.nc) return;
     const int n0 = B.n[0], n1 = B.n[1], n2 = B.n[2];
     const int i = (int)(p % n0), j = (int)((p / n0) % n1), k = (int)(p / ((int64_t)n0 * n1));
@@ -564,17 +915,13 @@ __global__ void __launch_bounds__(kBlock) advance_b_kernel(const BoxDev<R> *__re
 }
 
 // e <- e + dt curl b + alpha0 J (App. A.3.2 and A.2, eq. max2bis); J <- 0.
-// Also clears the overflow counters of the copy the push just read.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) advance_e_kernel(const BoxDev<R> *__restrict__ boxes,
-                                                           const CellBlock *__restrict__ blocks, R dt,
-                                                           int nsp, int clear_copy)
+                                                           const CellBlock *__restrict__ blocks, R dt)
 {
     using JT = typename JType<R>::T;
     const CellBlock cb = blocks[blockIdx.x];
     const BoxDev<R> &B = boxes[cb.box];
-    if (cb.first == 0 && threadIdx.x < (unsigned)nsp && clear_copy >= 0)
-        B.sp[threadIdx.x].cnt[clear_copy][B.ntiles] = 0;
     const int64_t p = (int64_t)cb.first + threadIdx.x;
     if (p >= B.nc) return;
     const int n0 = B.n[0], n1 = B.n[1], n2 = B.n[2];
@@ -599,23 +946,24 @@ __global__ void __launch_bounds__(kBlock) advance_e_kernel(const BoxDev<R> *__re
 
 // ------------------------------------------------------ counting-sort repack
 
+// The particles of a work item in copy c: a tile's A and B ranges (one block
+// striding), or the overflow region (kOvfBlocks blocks striding).
 template <typename R>
-__device__ inline void seg_range(const BoxDev<R> &B, const SpeciesDev<R> &S, int copy, int tile, int &start,
-                                 int &n, int &first, int &stride)
+__device__ inline TileRanges item_range(const BoxDev<R> &B, const SpeciesDev<R> &S, int c, int tile, int &first,
+                                        int &stride)
 {
     if (tile >= 0) {
-        start = S.seg_start[copy][tile];
-        n = min(S.cnt[copy][tile], S.seg_cap[copy][tile]);
         first = threadIdx.x;
         stride = kBlock;
-    } else {
-        start = S.seg_start[copy][B.ntiles];
-        n = min(S.cnt[copy][B.ntiles], S.ovf_cap);
-        first = (-1 - tile) * kBlock + threadIdx.x;
-        stride = kBlock * kOvfBlocks;
+        return tile_ranges(S, c, tile);
     }
+    first = (-1 - tile) * kBlock + threadIdx.x;
+    stride = kBlock * kOvfBlocks;
+    return overflow_range(B, S, c);
 }
 
+// Tile counts for the repack: a tile's ranges hold only particles of that
+// tile, so they count as a whole; overflow particles one by one.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) repack_count_kernel(const BoxDev<R> *__restrict__ boxes,
                                                               const Item *__restrict__ items, int nsp, int cur)
@@ -624,10 +972,13 @@ __global__ void __launch_bounds__(kBlock) repack_count_kernel(const BoxDev<R> *_
     const BoxDev<R> &B = boxes[it.box];
     for (int s = 0; s < nsp; ++s) {
         const SpeciesDev<R> &S = B.sp[s];
-        int start, n, first, stride;
-        seg_range(B, S, cur, it.tile, start, n, first, stride);
-        for (int p = first; p < n; p += stride)
-            atomicAdd(&S.tcount[tile_of(B, S.buf[cur].cell[start + p])], 1);
+        int first, stride;
+        const TileRanges r = item_range(B, S, cur, it.tile, first, stride);
+        if (it.tile >= 0) {
+            if (threadIdx.x == 0 && r.n > 0) atomicAdd(&S.tcount[it.tile], r.n);
+        } else {
+            for (int p = first; p < r.n; p += stride) atomicAdd(&S.tcount[tile_of(B, S.buf[cur].cell[r.slot(p)])], 1);
+        }
     }
 }
 
@@ -669,7 +1020,7 @@ __global__ void __launch_bounds__(kBlock) repack_layout_kernel(const BoxDev<R> *
     __syncthreads();
     const long long region = (long long)S.slots - S.ovf_cap;
     if (total > region) {                              // uniform: the whole block leaves
-        if (tid == 0) atomicOr(flags, PIC_FLAG_LOST);
+        if (tid == 0) atomicOr((PIC_GLOBAL uint32_t *)flags, PIC_FLAG_LOST);
         return;
     }
     const long long freeslots = region - total;
@@ -689,14 +1040,16 @@ __global__ void __launch_bounds__(kBlock) repack_layout_kernel(const BoxDev<R> *
         const long long cap = S.tcount[t] + (freeslots * (S.tcount[t] + 1)) / den;
         S.seg_start[dst][t] = (int32_t)run;
         S.seg_cap[dst][t] = (int32_t)cap;
-        S.cnt[dst][t] = 0;
+        S.na[dst][t] = 0;
+        S.nb[dst][t] = 0;
+        S.bs[dst][t] = 0;
         S.tcount[t] = 0;
         run += cap;
     }
     if (tid == 0) {
         S.seg_start[dst][nt] = S.slots - S.ovf_cap;
         S.seg_cap[dst][nt] = S.ovf_cap;
-        S.cnt[dst][nt] = 0;
+        S.nb[dst][nt] = 0;
     }
 }
 
@@ -709,8 +1062,9 @@ __global__ void __launch_bounds__(kBlock) repack_scatter_kernel(const BoxDev<R> 
     const BoxDev<R> &B = boxes[it.box];
     for (int s = 0; s < nsp; ++s) {
         const SpeciesDev<R> &S = B.sp[s];
-        int start, n, first, stride;
-        seg_range(B, S, cur, it.tile, start, n, first, stride);
+        int first, stride;
+        const TileRanges r = item_range(B, S, cur, it.tile, first, stride);
+        const int n = r.n;
         const PBuf<R> &P = S.buf[cur];
         // wave-uniform trip count so that the ballots in store_particle see every lane
         const int trips = n > first - (int)threadIdx.x ? (n - (first - (int)threadIdx.x) + stride - 1) / stride : 0;
@@ -720,12 +1074,12 @@ __global__ void __launch_bounds__(kBlock) repack_scatter_kernel(const BoxDev<R> 
             int32_t cell = 0, id = 0;
             R d[3] = {R(0), R(0), R(0)}, u[3] = {R(0), R(0), R(0)};
             if (valid) {
-                const int idx = start + p;
+                const int idx = r.slot(p);
                 cell = P.cell[idx];
                 for (int a = 0; a < 3; ++a) { d[a] = P.d[a][idx]; u[a] = P.u[a][idx]; }
                 if (P.id) id = P.id[idx];
             }
-            store_particle(B, S, cur ^ 1, tile_of(B, cell), valid, cell, d, u, id, flags);
+            store_particle(B, S, cur ^ 1, tile_of(B, cell), valid, cell, d, u, id, (PIC_GLOBAL uint32_t *)flags);
         }
     }
 }
@@ -768,9 +1122,11 @@ __global__ void __launch_bounds__(kBlock) clear_counts_kernel(const BoxDev<R> *_
     for (int t = blockIdx.x * kBlock + threadIdx.x; t <= B.ntiles; t += gridDim.x * kBlock)
         for (int s = 0; s < nsp; ++s) {
             const SpeciesDev<R> &S = B.sp[s];
-            S.cnt[old][t] = 0;
             S.seg_start[old][t] = S.seg_start[old ^ 1][t];
             S.seg_cap[old][t] = S.seg_cap[old ^ 1][t];
+            S.bs[old][t] = t < B.ntiles ? tile_ranges(S, old ^ 1, t).n : 0;
+            S.na[old][t] = 0;
+            S.nb[old][t] = 0;
         }
 }
 
@@ -804,12 +1160,12 @@ __global__ void __launch_bounds__(kBlock) diag_particles_kernel(const BoxDev<R> 
     const R hdt = R(0.5) * C.dt;
     for (int s = 0; s < C.nsp; ++s) {
         const SpeciesDev<R> &S = B.sp[s];
-        int start, n, first, stride;
-        seg_range(B, S, C.cur, it.tile, start, n, first, stride);
+        int first, stride;
+        const TileRanges r = item_range(B, S, C.cur, it.tile, first, stride);
         const PBuf<R> &P = S.buf[C.cur];
         double acc[6] = {0, 0, 0, 0, 0, 0};
-        for (int p = first; p < n; p += stride) {
-            const int idx = start + p;
+        for (int p = first; p < r.n; p += stride) {
+            const int idx = r.slot(p);
             const int32_t cell = P.cell[idx];
             const int ix = cell_x(cell), iy = cell_y(cell), iz = cell_z(cell);
             R d[3] = {P.d[0][idx], P.d[1][idx], P.d[2][idx]};
@@ -907,16 +1263,15 @@ template <typename R>
 hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R dt, int nsp,
                          int clear_copy, hipStream_t st)
 {
-    hipLaunchKernelGGL(advance_b_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt);
-    hipLaunchKernelGGL(advance_e_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt, nsp,
-                       clear_copy);
+    hipLaunchKernelGGL(advance_b_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt, nsp, clear_copy);
+    hipLaunchKernelGGL(advance_e_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_advance_b(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R h, hipStream_t st)
 {
-    hipLaunchKernelGGL(advance_b_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, h);
+    hipLaunchKernelGGL(advance_b_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, h, 0, -1);
     return hipGetLastError();
 }
 

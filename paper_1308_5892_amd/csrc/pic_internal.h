@@ -130,8 +130,10 @@ __device__ inline int wrap_idx(int i, int n)
 template <typename R>
 __device__ inline int tile_of(const BoxDev<R> &B, int32_t c)
 {
+    // tile counts are below 2^11, so 24-bit multiplies are exact
+    const unsigned ty = (unsigned)(cell_y(c) >> B.tshift[1]), tz = (unsigned)(cell_z(c) >> B.tshift[2]);
     return (cell_x(c) >> B.tshift[0]) +
-           B.ntile[0] * ((cell_y(c) >> B.tshift[1]) + B.ntile[1] * (cell_z(c) >> B.tshift[2]));
+           (int)__umul24((unsigned)B.ntile[0], ty + __umul24((unsigned)B.ntile[1], tz));
 }
 
 // cell blocks of the field kernels: (box, first cell) of kBlock cells

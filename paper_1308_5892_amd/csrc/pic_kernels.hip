@@ -344,20 +344,29 @@ __host__ __device__ inline size_t queue_bytes()
     return (size_t)kWaves * kQCap * (sizeof(int32_t) + 6 * sizeof(R));
 }
 
-// Bytes of dynamic LDS for a tile with edges (t0, t1, t2): node fields, the
-// piece queues, then a region that first holds the raw staged fields and then
-// the tile current.
+// Bytes of dynamic LDS for a tile with edges (t0, t1, t2): the trilinear
+// coefficients of every cell (48 values), the piece queues, then a region that
+// first holds the staged raw fields and node fields and then the tile current.
 template <typename R>
 __host__ __device__ inline size_t tile_lds_bytes(int t0, int t1, int t2)
 {
+    const size_t nc = (size_t)t0 * t1 * t2;
     const size_t nn = (size_t)(t0 + 1) * (t1 + 1) * (t2 + 1);
     const size_t jn = (size_t)(t0 + 3) * (t1 + 3) * (t2 + 3);
     const size_t bn = (size_t)(t0 + 2) * (t1 + 2) * (t2 + 2);
-    const size_t raw = 3 * (jn + bn) * sizeof(R);
+    const size_t raw = (3 * (jn + bn) + 6 * nn) * sizeof(R);
     const size_t jb = 3 * jn * sizeof(typename JType<R>::T);
     const size_t u = raw > jb ? raw : jb;
-    return nn * 8 * sizeof(R) + queue_bytes<R>() + ((u + 15) & ~size_t(15));
+    return nc * 48 * sizeof(R) + queue_bytes<R>() + ((u + 15) & ~size_t(15));
 }
+
+// q / m for 0 <= q < 4096 and 1 <= m <= 16, with mul = 65536 / m + 1: the
+// rounding error q (mul - 65536/m) / 65536 < 1/16 never reaches the next
+// integer because q/m is at least 1/m below it.
+__device__ inline int div_small(int q, int mul) { return (int)(__umul24((unsigned)q, (unsigned)mul) >> 16); }
+
+// v wrapped into [0, n) for v in [-n, 2n) (one correction step)
+__device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // The twelve face values of one piece (App. A.3.4, eq. current_dep), added to
 // the tile current at jl[cb + off[a][f]]: component a, faces (pp, qq) in
@@ -407,31 +416,50 @@ __device__ inline int neighbor_tile(const BoxDev<R> &B, const TileGeom<R> &g, in
     return t;
 }
 
-// Direction code of a particle in cell c (tile tn) relative to tile g: 13 if it
-// is inside g, the code of the adjacent tile it sits in, or -1 when neither
-// holds.  A pure function of the stored cell, so that the push and the
-// hand-over of the leavers classify a particle the same way.
+// Cells just outside tile g along each axis (wrapped into the box).
+struct TileRim {
+    int lo[3], hi[3];
+};
+
 template <typename R>
-__device__ inline int move_bin(const BoxDev<R> &B, const TileGeom<R> &g, int tn, const int c[3])
+__device__ inline TileRim tile_rim(const BoxDev<R> &B, const TileGeom<R> &g)
 {
-    int code = 0, mul = 1;
+    TileRim r;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const int rel = c[a] - g.o[a];
-        int dl;
-        if (rel >= 0 && rel < g.ext[a]) dl = 0;
-        else if (c[a] == wrap_idx(g.o[a] - 1, B.n[a])) dl = -1;
-        else if (c[a] == wrap_idx(g.o[a] + g.ext[a], B.n[a])) dl = 1;
-        else return -1;
+        r.lo[a] = g.o[a] == 0 ? B.n[a] - 1 : g.o[a] - 1;
+        r.hi[a] = g.o[a] + g.ext[a] == B.n[a] ? 0 : g.o[a] + g.ext[a];
+    }
+    return r;
+}
+
+// Direction code of a particle in cell c relative to tile g: 13 if it is
+// inside g, (dx+1) + 3(dy+1) + 9(dz+1) for a cell in the layer around g (the
+// adjacent tile in that direction is then the particle's tile, since a cell
+// one step outside a tile lies in the next tile along that axis), or -1
+// otherwise.  A pure function of the stored cell, so that the push and the
+// hand-over of the leavers classify a particle the same way.
+template <typename R>
+__device__ inline int move_bin(const TileGeom<R> &g, const TileRim &rim, const int c[3])
+{
+    int code = 0, mul = 1;
+    bool bad = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int dl = (unsigned)(c[a] - g.o[a]) < (unsigned)g.ext[a] ? 0
+                       : (c[a] == rim.lo[a] ? -1 : (c[a] == rim.hi[a] ? 1 : 2));
+        bad |= dl == 2;
         code += (dl + 1) * mul;
         mul *= 3;
     }
-    if (code != 13 && neighbor_tile(B, g, code) != tn) return -1;
-    return code;
+    return bad ? -1 : code;
 }
 
+template <typename R> struct PushWaves { static constexpr int value = 4; };
+template <> struct PushWaves<double> { static constexpr int value = 2; };
+
 template <typename R>
-__global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restrict__ boxes,
+__global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const BoxDev<R> *__restrict__ boxes,
                                                       const Item *__restrict__ items, StepConst<R> C);
 
 // Overflow sweep: same physics, fields from HBM, current by global atomics.
@@ -486,8 +514,11 @@ __device__ void push_overflow(const BoxDev<R> &B, int kblk, const StepConst<R> &
     }
 }
 
+// FP32 form: four waves per SIMD (at most 128 VGPRs), the occupancy that
+// hides the latency of the LDS gather and of the particle loads best on
+// gfx950.  FP64 form: two (its doubled registers would spill at four).
 template <typename R>
-__global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restrict__ boxes,
+__global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const BoxDev<R> *__restrict__ boxes,
                                                       const Item *__restrict__ items, StepConst<R> C)
 {
     using JT = typename JType<R>::T;
@@ -501,12 +532,18 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
     const int T = it.tile;
     const int tid = threadIdx.x;
     const TileGeom<R> g = tile_geom(B, T);
-    R *node = reinterpret_cast<R *>(smem);
-    unsigned char *qmem = smem + (((size_t)g.NN * 8 * sizeof(R) + 15) & ~size_t(15));
+    const TileRim rim = tile_rim(B, g);
+    // LDS: per-cell trilinear coefficients | piece queues | union of {raw e,
+    // raw b, node fields} (set-up) and the tile current (particle loop)
+    const int tsx = B.tshift[0], tsxy = B.tshift[0] + B.tshift[1];
+    const int ncoef = 48 << (B.tshift[0] + B.tshift[1] + B.tshift[2]);
+    R *coef = reinterpret_cast<R *>(smem);
+    unsigned char *qmem = smem + (((size_t)ncoef * sizeof(R) + 15) & ~size_t(15));
     unsigned char *uni = qmem + queue_bytes<R>();
     R *re = reinterpret_cast<R *>(uni);          // raw e, 3 x JN, origin o-1
     R *rb = re + 3 * g.JN;                        // raw b, 3 x BN, origin o-1
-    JT *jl = reinterpret_cast<JT *>(uni);         // J, 3 x JN, origin o-1 (after staging)
+    R *node = rb + 3 * g.BN;                      // node fields, 6 x NN, origin o
+    JT *jl = reinterpret_cast<JT *>(uni);         // J, 3 x JN, origin o-1 (after set-up)
 
     // re-binning counters: per species the stayers (from the front of the
     // tile's new A range), the leavers (staged from the back) and the leavers
@@ -520,70 +557,112 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
     if (tid < kMaxSpecies * 27) (&sh_bin[0][0])[tid] = 0;
     int nsp_n[kMaxSpecies];
 
-    // 1. stage e^t and b^{t-dt/2} of the tile and its halo
+    // region indices are decoded by multiply-shift (edges of at most 11 and
+    // fewer than 2^11 points: exact)
+    const int mJX = 65536 / g.JX + 1, mJY = 65536 / g.JY + 1;
+    const int mBX = 65536 / g.BX + 1, mBY = 65536 / g.BY + 1;
+    const int mNX = 65536 / g.NX + 1, mNY = 65536 / g.NY + 1;
+    const int JX = g.JX, JXY = g.JX * g.JY, BX = g.BX, BXY = g.BX * g.BY;
+    const int NX = g.NX, NXY = g.NX * g.NY;
     const int64_t n0 = B.n[0], n01 = (int64_t)B.n[0] * B.n[1];
-    for (int q = tid; q < 3 * g.JN; q += kBlock) {
-        const int c = q / g.JN, r = q - c * g.JN;
-        const int i = r % g.JX, j = (r / g.JX) % g.JY, k = r / (g.JX * g.JY);
-        const int gi = wrap_idx(g.o[0] - 1 + i, B.n[0]), gj = wrap_idx(g.o[1] - 1 + j, B.n[1]),
-                  gk = wrap_idx(g.o[2] - 1 + k, B.n[2]);
-        re[q] = B.e[c * B.nc + gi + n0 * gj + n01 * gk];
+    // grid index of the point (o-1) + (i,j,k), wrapped periodically
+    auto gidx = [&](int i, int j, int k) -> int64_t {
+        const int gi = wrap1(g.o[0] - 1 + i, B.n[0]), gj = wrap1(g.o[1] - 1 + j, B.n[1]),
+                  gk = wrap1(g.o[2] - 1 + k, B.n[2]);
+        if ((unsigned)gi >= (unsigned)B.n[0] || (unsigned)gj >= (unsigned)B.n[1] ||
+            (unsigned)gk >= (unsigned)B.n[2])   // boxes narrower than the halo
+            return wrap_idx(g.o[0] - 1 + i, B.n[0]) + n0 * wrap_idx(g.o[1] - 1 + j, B.n[1]) +
+                   n01 * wrap_idx(g.o[2] - 1 + k, B.n[2]);
+        return gi + n0 * gj + n01 * gk;
+    };
+
+    // 1. stage e^t and b^{t-dt/2} of the tile and its halo
+    for (int q = tid; q < g.JN; q += kBlock) {
+        const int jk = div_small(q, mJX), i = q - jk * JX;
+        const int k = div_small(jk, mJY), j = jk - k * g.JY;
+        const int64_t gp = gidx(i, j, k);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) re[c * g.JN + q] = B.e[c * B.nc + gp];
     }
-    for (int q = tid; q < 3 * g.BN; q += kBlock) {
-        const int c = q / g.BN, r = q - c * g.BN;
-        const int i = r % g.BX, j = (r / g.BX) % g.BY, k = r / (g.BX * g.BY);
-        const int gi = wrap_idx(g.o[0] - 1 + i, B.n[0]), gj = wrap_idx(g.o[1] - 1 + j, B.n[1]),
-                  gk = wrap_idx(g.o[2] - 1 + k, B.n[2]);
-        rb[q] = B.b[c * B.nc + gi + n0 * gj + n01 * gk];
+    for (int q = tid; q < g.BN; q += kBlock) {
+        const int jk = div_small(q, mBX), i = q - jk * BX;
+        const int k = div_small(jk, mBY), j = jk - k * g.BY;
+        const int64_t gp = gidx(i, j, k);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rb[c * g.BN + q] = B.b[c * B.nc + gp];
     }
     __syncthreads();
 
     // 2. b^t = b^{t-dt/2} - (dt/2) curl e^t (App. A.3.1 item 1), in place
     const R hdt = R(0.5) * C.dt;
     {
-        const int JX = g.JX, JXY = g.JX * g.JY;
-        for (int q = tid; q < 3 * g.BN; q += kBlock) {
-            const int c = q / g.BN, r = q - c * g.BN;
-            const int i = r % g.BX, j = (r / g.BX) % g.BY, k = r / (g.BX * g.BY);
+        const R *ex = re, *ey = re + g.JN, *ez = re + 2 * g.JN;
+        for (int q = tid; q < g.BN; q += kBlock) {
+            const int jk = div_small(q, mBX), i = q - jk * BX;
+            const int k = div_small(jk, mBY), j = jk - k * g.BY;
             const int p = i + JX * j + JXY * k;
-            const R *ex = re, *ey = re + g.JN, *ez = re + 2 * g.JN;
-            R curl;
-            if (c == 0) curl = (ez[p + JX] - ez[p]) - (ey[p + JXY] - ey[p]);
-            else if (c == 1) curl = (ex[p + JXY] - ex[p]) - (ez[p + 1] - ez[p]);
-            else curl = (ey[p + 1] - ey[p]) - (ex[p + JX] - ex[p]);
-            rb[q] -= hdt * curl;
+            rb[q] -= hdt * ((ez[p + JX] - ez[p]) - (ey[p + JXY] - ey[p]));
+            rb[g.BN + q] -= hdt * ((ex[p + JXY] - ex[p]) - (ez[p + 1] - ez[p]));
+            rb[2 * g.BN + q] -= hdt * ((ey[p + 1] - ey[p]) - (ex[p + JX] - ex[p]));
         }
     }
     __syncthreads();
 
     // 3. node fields on the (ext+1)^3 nodes of the tile (App. A.3.3)
     {
-        const int JX = g.JX, JXY = g.JX * g.JY, BX = g.BX, BXY = g.BX * g.BY;
         const R *ex = re, *ey = re + g.JN, *ez = re + 2 * g.JN;
         const R *bx = rb, *by = rb + g.BN, *bz = rb + 2 * g.BN;
         for (int q = tid; q < g.NN; q += kBlock) {
-            const int i = q % g.NX, j = (q / g.NX) % g.NY, k = q / (g.NX * g.NY);
+            const int jk = div_small(q, mNX), i = q - jk * NX;
+            const int k = div_small(jk, mNY), j = jk - k * g.NY;
             // raw coordinates of node (i,j,k) are (i+1, j+1, k+1)
             const int pe = (i + 1) + JX * (j + 1) + JXY * (k + 1);
             const int pb = (i + 1) + BX * (j + 1) + BXY * (k + 1);
-            R *nf = node + 8 * q;
-            nf[0] = R(0.5) * (ex[pe - 1] + ex[pe]);
-            nf[1] = R(0.5) * (ey[pe - JX] + ey[pe]);
-            nf[2] = R(0.5) * (ez[pe - JXY] + ez[pe]);
-            nf[3] = R(0.25) * (bx[pb] + bx[pb - BX] + bx[pb - BX - BXY] + bx[pb - BXY]);
-            nf[4] = R(0.25) * (by[pb] + by[pb - BXY] + by[pb - 1 - BXY] + by[pb - 1]);
-            nf[5] = R(0.25) * (bz[pb] + bz[pb - 1] + bz[pb - 1 - BX] + bz[pb - BX]);
-            nf[6] = R(0);
-            nf[7] = R(0);
+            node[q] = R(0.5) * (ex[pe - 1] + ex[pe]);
+            node[g.NN + q] = R(0.5) * (ey[pe - JX] + ey[pe]);
+            node[2 * g.NN + q] = R(0.5) * (ez[pe - JXY] + ez[pe]);
+            node[3 * g.NN + q] = R(0.25) * (bx[pb] + bx[pb - BX] + bx[pb - BX - BXY] + bx[pb - BXY]);
+            node[4 * g.NN + q] = R(0.25) * (by[pb] + by[pb - BXY] + by[pb - 1 - BXY] + by[pb - 1]);
+            node[5 * g.NN + q] = R(0.25) * (bz[pb] + bz[pb - 1] + bz[pb - 1 - BX] + bz[pb - BX]);
+        }
+    }
+    __syncthreads();
+
+    // 4. per cell and component, the trilinear interpolant of the eight node
+    //    values as c0 + c1 x + c2 y + c3 z + c4 xy + c5 yz + c6 zx + c7 xyz in
+    //    the in-cell offsets (the same polynomial, 8 instead of 16 operations
+    //    per component at the particle)
+    {
+        const int ncell = g.ext[0] * g.ext[1] * g.ext[2];
+        const int mEX = 65536 / g.ext[0] + 1, mEY = 65536 / g.ext[1] + 1;
+        for (int q = tid; q < ncell; q += kBlock) {
+            const int jk = div_small(q, mEX), i = q - jk * g.ext[0];
+            const int k = div_small(jk, mEY), j = jk - k * g.ext[1];
+            R *cf = coef + 48 * (i | (j << tsx) | (k << tsxy));
+            const int m = i + NX * j + NXY * k;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const R *F = node + c * g.NN + m;
+                const R f000 = F[0], f100 = F[1], f010 = F[NX], f110 = F[1 + NX];
+                const R f001 = F[NXY], f101 = F[1 + NXY], f011 = F[NX + NXY], f111 = F[1 + NX + NXY];
+                const R ax = f100 - f000, ay = f010 - f000, az = f001 - f000;
+                const R axy = (f110 - f010) - ax, ayz = (f011 - f001) - ay, azx = (f101 - f100) - az;
+                cf[8 * c + 0] = f000;
+                cf[8 * c + 1] = ax;
+                cf[8 * c + 2] = ay;
+                cf[8 * c + 3] = az;
+                cf[8 * c + 4] = axy;
+                cf[8 * c + 5] = ayz;
+                cf[8 * c + 6] = azx;
+                cf[8 * c + 7] = ((f111 - f011) - (f101 - f001)) - axy;
+            }
         }
     }
     __syncthreads();
     for (int q = tid; q < 3 * g.JN; q += kBlock) jl[q] = JT(0);
     __syncthreads();
 
-    // 4. particles of every species: gather, push, move, deposit, re-bin
-    const int NX = g.NX, NXY = g.NX * g.NY;
-    const int JX = g.JX, JXY = g.JX * g.JY;
+    // 5. particles of every species: gather, push, move, deposit, re-bin
     // uniform index offsets of the twelve faces of a piece (see deposit_piece)
     int joff[3][4];
     {
@@ -666,26 +745,22 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
             // HBM path instead
             const bool inside = (unsigned)lx < (unsigned)g.ext[0] && (unsigned)ly < (unsigned)g.ext[1] &&
                                 (unsigned)lz < (unsigned)g.ext[2];
-            // gather: trilinear weights on the eight nodes of the cell
+            // gather: the cell's trilinear interpolant at the in-cell offset
             R E[3] = {R(0), R(0), R(0)}, Bf[3] = {R(0), R(0), R(0)};
             if (!inside) {
                 gather_global(B, ix, iy, iz, d, hdt, E, Bf);
             } else {
-                const R wx[2] = {R(1) - d[0], d[0]}, wy[2] = {R(1) - d[1], d[1]}, wz[2] = {R(1) - d[2], d[2]};
-                const int q0 = lx + NX * ly + NXY * lz;
+                const R *cf = coef + 48 * (lx | (ly << tsx) | (lz << tsxy));
+                const R pxy = d[0] * d[1], pyz = d[1] * d[2], pzx = d[2] * d[0], pxyz = pxy * d[2];
+                R F[6];
 #pragma unroll
-                for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-                    for (int jj = 0; jj < 2; ++jj) {
-                        const R wyz = wy[jj] * wz[kk];
-#pragma unroll
-                        for (int ii = 0; ii < 2; ++ii) {
-                            const R w = wx[ii] * wyz;
-                            const R *nf = node + 8 * (q0 + ii + NX * jj + NXY * kk);
-                            E[0] += w * nf[0]; E[1] += w * nf[1]; E[2] += w * nf[2];
-                            Bf[0] += w * nf[3]; Bf[1] += w * nf[4]; Bf[2] += w * nf[5];
-                        }
-                    }
+                for (int c = 0; c < 6; ++c) {
+                    const R *k8 = cf + 8 * c;
+                    F[c] = k8[0] + d[0] * k8[1] + d[1] * k8[2] + d[2] * k8[3] + pxy * k8[4] + pyz * k8[5] +
+                           pzx * k8[6] + pxyz * k8[7];
+                }
+                E[0] = F[0]; E[1] = F[1]; E[2] = F[2];
+                Bf[0] = F[3]; Bf[1] = F[4]; Bf[2] = F[5];
             }
             boris(hk, E, Bf, u);
             if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]))) {
@@ -748,7 +823,7 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
             // tile's new A range, leavers into an adjacent tile are staged from
             // the back (both claimed with one LDS atomic per wave); anything
             // else claims its target's B range with a global atomic
-            const int bin = valid ? move_bin(B, g, tn, cn) : -1;
+            const int bin = valid ? move_bin(g, rim, cn) : -1;
             const bool stay = bin == 13, lv = bin >= 0 && bin != 13;
             const uint64_t ms = __ballot(stay), ml = __ballot(lv);
             const int sl = ms ? __ffsll((unsigned long long)ms) - 1 : 0;
@@ -772,7 +847,7 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
 
             // deposit: the first piece (in the home cell) at once, later pieces
             // through the wave's queue
-            const int jb = (lx + 1) + JX * (ly + 1) + JXY * (lz + 1);
+            const int jb = (lx + 1) + __mul24(JX, ly + 1) + __mul24(JXY, lz + 1);
             R p1[3];
             if (nb == 0) {
                 p1[0] = x1[0]; p1[1] = x1[1]; p1[2] = x1[2];
@@ -811,7 +886,7 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
                         qval[(3 + a) * kQCap + pos] = pe[a] - ps[a];
                         qval[a * kQCap + pos] = sv[a];
                     }
-                    qidx[pos] = (jb + offc[0] + JX * offc[1] + JXY * offc[2]) | sgnbit;
+                    qidx[pos] = (jb + offc[0] + __mul24(JX, offc[1]) + __mul24(JXY, offc[2])) | sgnbit;
                 }
                 qcount += (int)__popcll(mh);
                 ps[0] = pe[0]; ps[1] = pe[1]; ps[2] = pe[2];
@@ -823,19 +898,20 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
     while (qcount > 0) drain(64);
     __syncthreads();
 
-    // 5. flush the tile current to HBM (integer sums: order-independent)
-    for (int q = tid; q < 3 * g.JN; q += kBlock) {
-        const JT v = jl[q];
-        if (v != JT(0)) {
-            const int c = q / g.JN, r = q - c * g.JN;
-            const int i = r % g.JX, j = (r / g.JX) % g.JY, k = r / (g.JX * g.JY);
-            const int gi = wrap_idx(g.o[0] - 1 + i, B.n[0]), gj = wrap_idx(g.o[1] - 1 + j, B.n[1]),
-                      gk = wrap_idx(g.o[2] - 1 + k, B.n[2]);
-            atomic_add_global(&B.J[c * B.nc + gi + n0 * gj + n01 * gk], v);
+    // 6. flush the tile current to HBM (integer sums: order-independent)
+    for (int q = tid; q < g.JN; q += kBlock) {
+        const JT v0 = jl[q], v1 = jl[g.JN + q], v2 = jl[2 * g.JN + q];
+        if (v0 != JT(0) || v1 != JT(0) || v2 != JT(0)) {
+            const int jk = div_small(q, mJX), i = q - jk * JX;
+            const int k = div_small(jk, mJY), j = jk - k * g.JY;
+            const int64_t gp = gidx(i, j, k);
+            if (v0 != JT(0)) atomic_add_global(&B.J[gp], v0);
+            if (v1 != JT(0)) atomic_add_global(&B.J[B.nc + gp], v1);
+            if (v2 != JT(0)) atomic_add_global(&B.J[2 * B.nc + gp], v2);
         }
     }
 
-    // 6. hand the staged leavers over to the adjacent tiles: one global atomic
+    // 7. hand the staged leavers over to the adjacent tiles: one global atomic
     //    per (species, direction) claims their slots in that tile's B range
     const int dst = C.cur ^ 1;
     if (tid < C.nsp * 27) {
@@ -858,8 +934,8 @@ __global__ void __launch_bounds__(kBlock) push_kernel(const BoxDev<R> *__restric
             const R u[3] = {Q.u[0][from], Q.u[1][from], Q.u[2][from]};
             const int32_t id = Q.id ? Q.id[from] : 0;
             const int c3[3] = {cell_x(cell), cell_y(cell), cell_z(cell)};
-            const int tn = tile_of(B, cell);
-            const int k = move_bin(B, g, tn, c3);      // the same bin as at staging
+            const int k = move_bin(g, rim, c3);         // the same bin as at staging
+            const int tn = neighbor_tile(B, g, k);      // the tile whose range was claimed
             const int rank = atomicAdd(&sh_bin[s][k], 1);
             const int at = b_range_slot(B, S, dst, tn, S.bs[dst][tn] + sh_base[s][k] + rank, C.flags);
             if (at >= 0) write_particle(Q, at, cell, d, u, id);

@@ -27,6 +27,15 @@ HARRIS = dict(name="double Harris sheet 512x256x4", dims=(512, 256, 4), ppc=64, 
               theta_e=1.0, gu_e=0.68, chi=1.0, n_x=15.0, rho0=128.0, background=0.1, dt=0.5,
               steps=2000, seed=4)
 
+# scaled-down shapes of the same workloads, small enough for element-wise
+# parity with the oracle over ten steps
+BEAMS_SMALL = dict(name="counter-streaming pair beams 32x32x4", dims=(32, 32, 4), ppc_per_beam=4,
+                   gamma=3.0, theta=0.01, n_x=20.0, rho0=16.0, dt=0.5, seed=3)
+HARRIS_SMALL = dict(name="double Harris sheet 64x32x4", dims=(64, 32, 4), ppc=4, mass_ratio=25.0,
+                    theta_e=1.0, gu_e=0.68, chi=1.0, n_x=4.0, rho0=8.0, background=0.1, dt=0.5, seed=4)
+ENSEMBLE_SMALL = dict(name="ensemble of 6 thermal boxes", n_boxes=6, edge=(6, 14), ppc=(1, 8),
+                      theta=(0.05, 1.0), n_x=10.0, dt=0.5, seed=6)
+
 # ensemble of independent thermal boxes, log-uniform sizes and densities
 ENSEMBLE = dict(name="ensemble of 256 thermal boxes", n_boxes=256, edge=(8, 32), ppc=(4, 256),
                 theta=(0.05, 1.0), n_x=10.0, dt=0.5, steps=500, seed=5)

@@ -14,28 +14,10 @@ from tests import gpu_cases as G
 pytestmark = pytest.mark.gpu
 
 
-def _oblique_mode(dims, m, dt):
-    E_POS = np.array([[0.5, 0, 0], [0, 0.5, 0], [0, 0, 0.5]])
-    B_POS = np.array([[0, 0.5, 0.5], [0.5, 0, 0.5], [0.5, 0.5, 0]])
-    kv = 2 * np.pi * np.array(m) / np.array(dims)
-    kap = 2 * np.sin(kv / 2)
-    e_hat = np.cross(kap, [0.3, 1.0, 0.2])
-    e_hat /= np.linalg.norm(e_hat)
-    s = 0.5 * dt * np.linalg.norm(kap)
-    om = 2 * np.arcsin(s) / dt
-    b_hat = dt * np.cross(kap, e_hat) / (2 * s)
-    i, j, k = np.meshgrid(*[np.arange(d) for d in dims], indexing="ij")
-    X = [a.transpose(2, 1, 0).reshape(-1).astype(float) for a in (i, j, k)]
-    e = np.concatenate([e_hat[c] * np.cos(sum(kv[a] * (X[a] + E_POS[c][a]) for a in range(3))) for c in range(3)])
-    b = np.concatenate([b_hat[c] * np.cos(sum(kv[a] * (X[a] + B_POS[c][a]) for a in range(3)) + om * dt / 2)
-                        for c in range(3)])
-    return e, b
-
-
 @pytest.mark.parametrize("fp64,tol", [(False, 2e-5), (True, 1e-12)])
 def test_vacuum_fields_match_oracle(fp64, tol):
     dims = (10, 12, 7)                       # ragged tiles on every axis
-    e0, b0 = _oblique_mode(dims, (1, 2, 1), 0.5)
+    e0, b0 = G.oblique_mode(dims, (1, 2, 1), 0.5)
     s = G.sim(dims, 10.0, 2.0, [1, 1], fp64=fp64)
     s.set_fields(0, e0, b0)
     st = G.oracle_state(dims, 10.0, 2.0)
@@ -67,14 +49,8 @@ def test_one_step_on_frozen_fields(fp64):
     s = G.sim(dims, 10.0, 40.0, [n, n], fp64=fp64)
     st = G.oracle_state(dims, 10.0, 40.0)
     e, b = G.random_fields(rng, int(np.prod(dims)), 0.05, 0.3)
-    s.set_fields(0, e, b)
-    xs, us = [], []
-    for sp in range(2):
-        x, u = _random_particles(rng, dims, n)
-        s.set_particles(0, sp, x, u, np.arange(n))
-        xs.append(x)
-        us.append(u)
-    G.copy_to_oracle(s, st)      # the oracle starts from the stored (rounded) state
+    # both start from the state rounded to the library's storage format
+    G.start(s, st, [_random_particles(rng, dims, n) for _ in range(2)], e=e, b=b, fp64=fp64)
     s.step(1)
     st.step(1)
     e1, b1, _ = s.fields(0)
@@ -105,10 +81,7 @@ def test_deposit_alone_equals_oracle_current():
     for fp64 in (False, True):
         s = G.sim(dims, 10.0, 16.0, [n, n], fp64=fp64)
         st = G.oracle_state(dims, 10.0, 16.0)
-        for sp in range(2):
-            x, u = _random_particles(rng, dims, n)
-            s.set_particles(0, sp, x, u, np.arange(n))
-        G.copy_to_oracle(s, st)
+        G.start(s, st, [_random_particles(rng, dims, n) for _ in range(2)], fp64=fp64)
         s.step(1)
         st.step(1)
         e1, _, _ = s.fields(0)
@@ -125,9 +98,11 @@ def test_thermal_pair_plasma_ten_steps(fp64, tol):
     dims, ppc = (16, 16, 16), 8
     npairs = ppc * int(np.prod(dims))
     s = G.sim(dims, 10.0, 2 * ppc, [npairs, npairs], fp64=fp64)
-    s.load(0, 0, 1, (0.1, 0.0, 1), (0.1, 0.0, 1), ppc, seed=1)
     st = G.oracle_state(dims, 10.0, 2 * ppc)
-    G.copy_to_oracle(s, st)
+    mj = {"theta": 0.1, "gb": 0.0, "axis": 1}
+    parts = G.oracle_loaded(dims, 0.5, 10.0, 2 * ppc, G.PAIR,
+                            [dict(seed=1, stream=0, npairs=npairs, A=mj, B=mj)])
+    G.start(s, st, parts, fp64=fp64)
     s.step(10)
     st.step(10)
     worst = 0.0
@@ -231,12 +206,13 @@ def test_overflow_region_keeps_parity():
     n = 6000
     s = G.sim(dims, 10.0, 16.0, [n, n], fp64=True, headroom=1.05)
     st = G.oracle_state(dims, 10.0, 16.0)
+    parts = []
     for sp in range(2):
         x = rng.uniform(0, 1, (n, 3)) * np.array([4.0, 8.0, 8.0])
         u = 0.05 * rng.standard_normal((n, 3))
         u[: n // 10, 0] += 3.0
-        s.set_particles(0, sp, x, u, np.arange(n))
-    G.copy_to_oracle(s, st)
+        parts.append((x, u))
+    G.start(s, st, parts, fp64=True)
     seen = 0
     for _ in range(12):
         s.step(1)
@@ -259,11 +235,7 @@ def test_tiny_and_odd_boxes(dims, tile):
     s = G.sim(dims, 10.0, 16.0, [n, n], fp64=True, tile=tile)
     st = G.oracle_state(dims, 10.0, 16.0)
     e, b = G.random_fields(rng, int(np.prod(dims)), 0.02, 0.2)
-    s.set_fields(0, e, b)
-    for sp in range(2):
-        x, u = _random_particles(rng, dims, n)
-        s.set_particles(0, sp, x, u, np.arange(n))
-    G.copy_to_oracle(s, st)
+    G.start(s, st, [_random_particles(rng, dims, n) for _ in range(2)], e=e, b=b, fp64=True)
     s.step(5)
     st.step(5)
     for sp in range(2):
@@ -289,9 +261,11 @@ def test_repack_keeps_parity():
     dims, ppc = (12, 8, 8), 4
     npairs = ppc * int(np.prod(dims))
     s = G.sim(dims, 10.0, 2 * ppc, [npairs, npairs], fp64=True, sort_interval=3)
-    s.load(0, 0, 1, (0.2, 0.3, 0), (0.2, -0.3, 0), ppc, seed=8)
     st = G.oracle_state(dims, 10.0, 2 * ppc)
-    G.copy_to_oracle(s, st)
+    parts = G.oracle_loaded(dims, 0.5, 10.0, 2 * ppc, G.PAIR,
+                            [dict(seed=8, stream=0, npairs=npairs, A={"theta": 0.2, "gb": 0.3, "axis": 0},
+                                  B={"theta": 0.2, "gb": -0.3, "axis": 0})])
+    G.start(s, st, parts, fp64=True)
     s.step(10)
     st.step(10)
     for sp in range(2):
@@ -343,13 +317,8 @@ def test_multiple_boxes_in_one_launch():
     states = []
     for bi, d in enumerate(dims_list):
         e, b = G.random_fields(rng, int(np.prod(d)), 0.02, 0.2)
-        sim.set_fields(bi, e, b)
-        for sp in range(2):
-            x, u = _random_particles(rng, d, n)
-            sim.set_particles(bi, sp, x, u, np.arange(n))
-    for bi, d in enumerate(dims_list):
         st = O.State(d, 0.5, 10.0, 8.0, G.PAIR)
-        G.copy_to_oracle(sim, st, bi)
+        G.start(sim, st, [_random_particles(rng, d, n) for _ in range(2)], box=bi, e=e, b=b, fp64=True)
         states.append(st)
     sim.step(4)
     for bi, st in enumerate(states):

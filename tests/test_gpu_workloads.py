@@ -1,0 +1,316 @@
+"""Parity of the HIP path with the FP64 oracle on the benchmark's workload
+families: thermal plasma (long-run energy), counter-streaming beams, the
+double Harris sheet and the batched ensemble - element by element at sizes the
+oracle runs in seconds, and on sampled outputs (plus properties that hold at
+any size) at the full workload sizes, in the benchmark's launch configuration
+(tiles of 4^3 cells, repack every 50 steps).
+
+Every start state comes from the test inputs or the oracle's own loader,
+rounded to the library's storage format and given to both sides.
+"""
+import numpy as np
+import pytest
+
+import pic_inputs as W
+from tests import gpu_cases as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _energy(d):
+    return d["W_E"].sum() + d["W_B"].sum() + d["K"].sum()
+
+
+def test_energy_drift_fp32_tracks_fp64_over_1000_steps():
+    # thermal pair plasma 16^3, 8 pairs/cell, theta = 0.1: the relative total
+    # energy drift of the FP32 / fixed-point form stays within 1e-3 of the
+    # FP64 form's over 1000 steps (both start from the same stored state)
+    w = W.THERMAL16
+    dims, ppc = w["dims"], w["ppc"]
+    npairs = ppc * int(np.prod(dims))
+    mj = {"theta": w["theta"], "gb": 0.0, "axis": 1}
+    parts = G.oracle_loaded(dims, w["dt"], w["n_x"], 2 * ppc, G.PAIR,
+                            [dict(seed=w["seed"], stream=0, npairs=npairs, A=mj, B=mj)])
+    parts = [G.to_storage(x, u, dims, False) for x, u in parts]
+    curves = {}
+    for fp64 in (False, True):
+        s = G.sim(dims, w["n_x"], 2 * ppc, [npairs, npairs], dt=w["dt"], fp64=fp64, sort_interval=50)
+        st = G.oracle_state(dims, w["n_x"], 2 * ppc, w["dt"])
+        G.start(s, st, parts, fp64=fp64)
+        e0 = _energy(s.diag(0))
+        c = []
+        for _ in range(10):
+            s.step(100)
+            d = s.diag(0)
+            assert d["flags"] == 0
+            c.append(_energy(d) / e0 - 1.0)
+        curves[fp64] = np.array(c)
+        s.close()
+    gap = np.abs(curves[False] - curves[True])
+    assert gap.max() < 1e-3, (curves[False], curves[True])
+    # the drift itself is the scheme's self-heating (Sect. 3.1.3), small and common to both
+    assert np.abs(curves[True]).max() < 2e-2, curves[True]
+
+
+def test_energy_curve_fp64_form_follows_oracle_100_steps():
+    w = W.THERMAL16
+    dims, ppc = w["dims"], w["ppc"]
+    npairs = ppc * int(np.prod(dims))
+    mj = {"theta": w["theta"], "gb": 0.0, "axis": 1}
+    parts = G.oracle_loaded(dims, w["dt"], w["n_x"], 2 * ppc, G.PAIR,
+                            [dict(seed=w["seed"], stream=0, npairs=npairs, A=mj, B=mj)])
+    s = G.sim(dims, w["n_x"], 2 * ppc, [npairs, npairs], dt=w["dt"], fp64=True)
+    st = G.oracle_state(dims, w["n_x"], 2 * ppc, w["dt"])
+    G.start(s, st, parts, fp64=True)
+    for _ in range(4):
+        s.step(25)
+        st.step(25)
+        d, r = s.diag(0), st.diag()
+        for k in ("W_E", "W_B", "K"):
+            assert np.allclose(d[k], r[k], rtol=1e-8, atol=1e-14 * _energy(r)), (k, d[k], r[k])
+    s.close()
+
+
+def _ten_steps(s, st, dims, tol, nsp=2, box=0):
+    s.step(10)
+    st.step(10)
+    worst = 0.0
+    for sp in range(nsp):
+        x, u, _ = s.particles(box, sp)
+        worst = max(worst, G.u_rel_err(u, st.u[st.species == sp], 1e-2).max())
+        assert np.abs(G.wrap_delta(x, st.x[st.species == sp], dims)).max() < 10 * tol
+    return worst
+
+
+@pytest.mark.parametrize("fp64,tol", [(False, 1e-5), (True, 1e-11)])
+def test_beams_ten_steps(fp64, tol):
+    w = W.BEAMS_SMALL
+    dims = w["dims"]
+    loads = G.beam_loads(w)
+    n = sum(ld["npairs"] for ld in loads)
+    s = G.sim(dims, w["n_x"], w["rho0"], [n, n], dt=w["dt"], fp64=fp64)
+    # the device loader draws the same two beams as the oracle's loader
+    for ld in loads:
+        s.load(0, 0, 1, (ld["A"]["theta"], ld["A"]["gb"], 0), (ld["B"]["theta"], ld["B"]["gb"], 0),
+               w["ppc_per_beam"], seed=ld["seed"], stream=ld["stream"])
+    parts = G.oracle_loaded(dims, w["dt"], w["n_x"], w["rho0"], G.PAIR, loads)
+    for sp in range(2):
+        x, u, _ = s.particles(0, sp)
+        assert np.abs(G.wrap_delta(x, parts[sp][0], dims)).max() < (1e-12 if fp64 else 2e-6)
+        assert G.u_rel_err(u, parts[sp][1], 1e-3).max() < (1e-9 if fp64 else 2e-7)
+    st = G.oracle_state(dims, w["n_x"], w["rho0"], w["dt"])
+    G.start(s, st, parts, fp64=fp64)
+    worst = _ten_steps(s, st, dims, tol)
+    assert worst < tol, worst
+    d = s.diag(0)
+    assert d["flags"] == 0 and d["count"].tolist() == [n, n]
+    s.close()
+
+
+@pytest.mark.parametrize("fp64,tol", [(False, 1e-5), (True, 1e-11)])
+def test_harris_sheet_ten_steps(fp64, tol):
+    w = W.HARRIS_SMALL
+    dims = w["dims"]
+    species, b, loads, gpu, hf = G.harris_setup(w)
+    n = sum(ld["npairs"] for ld in loads)
+    s = G.sim(dims, w["n_x"], w["rho0"], [n + 64, n + 64], dt=w["dt"], fp64=fp64, species=species)
+    s.harris_field(0, *hf)
+    for A, B, ppc, kw in gpu:
+        s.load(0, 0, 1, A, B, ppc, **kw)
+    parts = G.oracle_loaded(dims, w["dt"], w["n_x"], w["rho0"], species, loads, b=b)
+    for sp in range(2):
+        x, u, _ = s.particles(0, sp)
+        assert len(x) == n
+        assert np.abs(G.wrap_delta(x, parts[sp][0], dims)).max() < (1e-12 if fp64 else 2e-6)
+        assert G.u_rel_err(u, parts[sp][1], 1e-3).max() < (1e-9 if fp64 else 2e-6)
+    e, bg, _ = s.fields(0)
+    assert np.abs(bg - b).max() < (1e-15 if fp64 else 1e-7)
+    st = G.oracle_state(dims, w["n_x"], w["rho0"], w["dt"], species=species)
+    G.start(s, st, parts, b=b, fp64=fp64)
+    worst = _ten_steps(s, st, dims, tol)
+    assert worst < tol, worst
+    e1, b1, _ = s.fields(0)
+    ftol = 1e-12 if fp64 else 1e-5
+    assert np.abs(b1 - st.b).max() < ftol * np.abs(st.b).max()
+    assert np.abs(e1 - st.e).max() < 10 * ftol * max(np.abs(st.e).max(), 1e-30)
+    s.close()
+
+
+@pytest.mark.parametrize("fp64,tol", [(False, 1e-5), (True, 1e-11)])
+def test_ensemble_in_one_launch(fp64, tol):
+    from paper_1308_5892_amd import pic as P
+    spec = W.ENSEMBLE_SMALL
+    blist = W.ensemble_boxes(spec)
+    boxes = []
+    for bx in blist:
+        npairs = bx["ppc"] * int(np.prod(bx["dims"]))
+        boxes.append({"n": bx["dims"], "n_x": spec["n_x"], "rho0": 2.0 * bx["ppc"],
+                      "max_particles": [npairs, npairs]})
+    sim = P.Simulation(boxes, G.PAIR, spec["dt"], fp64=fp64, track_ids=True)
+    states = []
+    for bi, bx in enumerate(blist):
+        dims = bx["dims"]
+        npairs = bx["ppc"] * int(np.prod(dims))
+        mj = {"theta": bx["theta"], "gb": 0.0, "axis": 1}
+        parts = G.oracle_loaded(dims, spec["dt"], spec["n_x"], 2.0 * bx["ppc"], G.PAIR,
+                                [dict(seed=bx["seed"], stream=0, npairs=npairs, A=mj, B=mj)])
+        st = G.oracle_state(dims, spec["n_x"], 2.0 * bx["ppc"], spec["dt"])
+        G.start(sim, st, parts, box=bi, fp64=fp64)
+        states.append(st)
+    sim.step(10)
+    for bi, st in enumerate(states):
+        st.step(10)
+        for sp in range(2):
+            _, u, _ = sim.particles(bi, sp)
+            err = G.u_rel_err(u, st.u[st.species == sp], 1e-2).max()
+            assert err < tol, (bi, sp, err)
+        e, _, _ = sim.fields(bi)
+        assert np.abs(e - st.e).max() < (1e-12 if fp64 else 1e-4) * np.abs(st.e).max()
+    sim.close()
+
+
+# ----------------------------------------------------------- full sizes
+
+def _one_step_sampled(s, box, dims, dt, n_x, rho0, species, parts, e0, b0, rng, nsample=1024, nfaces=12):
+    """One step of the full-size state (parts, e0, b0: already in storage
+    form, also held by the GPU context) checked on sampled outputs the oracle
+    computes one by one from the same inputs: momenta and positions of sampled
+    particles (gather + Boris + move), b^{t+dt/2} everywhere, and the current
+    alpha0 J = e^{t+dt} - e^t - dt curl b^{t+dt/2} on sampled faces, from an
+    oracle deposit of every particle whose move can reach that face."""
+    from oracle import oracle as O
+    alpha0 = 2.0 / (n_x * n_x * rho0)
+    kq = [q / m for q, m in species]
+    sgn = [np.sign(q) for q, _ in species]
+    s.step(1)
+    e1, b1, _ = s.fields(box)
+    # b: no current, a plain stencil update of the inputs
+    bref = O.advance_b(dims, dt, e0, b0)
+    assert np.abs(b1 - bref).max() <= 2e-6 * max(np.abs(bref).max(), 1e-30) + 1e-12
+    bt = O.advance_b(dims, 0.5 * dt, e0, b0)
+    L = np.asarray(dims, dtype=float)
+
+    def push(sp, p):
+        x0, u0 = parts[sp][0][p], parts[sp][1][p]
+        E, B = O.gather(dims, e0, bt, x0)
+        u = O.boris(kq[sp], dt, E, B, u0)
+        return x0, u, x0 + dt * u / np.sqrt(1.0 + u @ u)
+
+    for sp in range(len(species)):
+        x1, u1, ids = s.particles(box, sp)
+        assert np.array_equal(ids, np.arange(len(parts[sp][0])))
+        for p in rng.choice(len(ids), size=min(nsample, len(ids)), replace=False):
+            _, u, x = push(sp, p)
+            assert np.linalg.norm(u1[p] - u) <= 2e-6 * max(np.linalg.norm(u), 1e-3), (sp, p, u1[p], u)
+            assert np.abs(G.wrap_delta(x1[p], x, dims)).max() < 2e-6, (sp, p, x1[p], x)
+    aJ = e1 - e0 - dt * O.curl_b(dims, b1)
+    n = int(np.prod(dims))
+    cells = [np.floor(parts[sp][0]).astype(np.int64) for sp in range(len(species))]
+    J = np.zeros(3 * n)
+    got, ref = [], []
+    for _ in range(nfaces):
+        c = int(rng.integers(3))
+        f = np.array([rng.integers(d) for d in dims])
+        J[:] = 0.0
+        for sp in range(len(species)):
+            # a piece of a move lies within one cell of the start cell; the face
+            # of component c at node f takes pieces from cells f - (0 or 1) off axis c
+            near = np.ones(len(cells[sp]), dtype=bool)
+            for a in range(3):
+                dlt = (cells[sp][:, a] - f[a]) % dims[a]
+                dlt = np.where(dlt > dims[a] // 2, dlt - dims[a], dlt)
+                near &= (dlt >= -2) & (dlt <= 1) if dims[a] > 4 else np.ones_like(near)
+            for p in np.nonzero(near)[0]:
+                x0, _, x = push(sp, p)
+                O.deposit_move(dims, sgn[sp], x0, x0 + G.wrap_delta(x, x0, dims), J)
+        idx = c * n + f[0] + dims[0] * (f[1] + dims[1] * f[2])
+        got.append(aJ[idx])
+        ref.append(alpha0 * J[idx])
+    got, ref = np.array(got), np.array(ref)
+    tol = 1e-5 * np.abs(ref).max() + 16 * 2.0 ** -24 * np.abs(e1).max()
+    assert np.abs(got - ref).max() <= tol, (got, ref)
+    return e1, b1
+
+
+def _full_size_check(s, w_dims, dt, n_x, rho0, species, parts, e0, b0, seed, rho_unit):
+    rng = np.random.default_rng(seed)
+    _one_step_sampled(s, 0, w_dims, dt, n_x, rho0, species, parts, e0, b0, rng)
+    # charge conservation of the deposit, a property at any size: the Gauss
+    # residual stays at its initial (roundoff) level over further steps
+    s.step(9)
+    d = s.diag(0)
+    assert d["flags"] == 0
+    assert d["gauss_max"] < 1e-4 * rho_unit, d["gauss_max"]
+    assert d["count"].tolist() == [len(p[0]) for p in parts]
+
+
+@pytest.mark.slow
+def test_full_size_thermal_64cubed():
+    w = W.THERMAL64
+    dims, ppc = w["dims"], w["ppc"]
+    npairs = ppc * int(np.prod(dims))
+    mj = {"theta": w["theta"], "gb": 0.0, "axis": 1}
+    from oracle import oracle as O
+    x, ua, ub = O.load_pairs(dims, w["seed"], 0, npairs, mj, mj)
+    e0, b0 = G.oblique_mode(dims, (1, 2, 1), w["dt"], amp=1e-3)
+    s = G.sim(dims, w["n_x"], 2 * ppc, [npairs, npairs], dt=w["dt"], sort_interval=50)
+    parts = [G.to_storage(x, ua, dims, False), G.to_storage(x, ub, dims, False)]
+    e0, b0 = G.field_storage(e0, False), G.field_storage(b0, False)
+    st = G.oracle_state(dims, w["n_x"], 2 * ppc, w["dt"])
+    G.start(s, st, parts, e=e0, b=b0)
+    del st
+    _full_size_check(s, dims, w["dt"], w["n_x"], 2 * ppc, G.PAIR, parts, e0, b0, 1,
+                     2.0 / (w["n_x"] ** 2 * 2 * ppc) * ppc)
+    s.close()
+
+
+@pytest.mark.slow
+def test_full_size_beams_256x256x4():
+    w = W.FILAMENT
+    dims = w["dims"]
+    loads = G.beam_loads(w)
+    from oracle import oracle as O
+    xs, ua, ub = [], [], []
+    for ld in loads:
+        x, a, b = O.load_pairs(dims, ld["seed"], ld["stream"], ld["npairs"], ld["A"], ld["B"])
+        xs.append(x)
+        ua.append(a)
+        ub.append(b)
+    x = np.concatenate(xs)
+    n = len(x)
+    e0, b0 = G.oblique_mode(dims, (2, 1, 0), w["dt"], amp=1e-3)
+    s = G.sim(dims, w["n_x"], w["rho0"], [n, n], dt=w["dt"], sort_interval=50)
+    parts = [G.to_storage(x, np.concatenate(ua), dims, False), G.to_storage(x, np.concatenate(ub), dims, False)]
+    e0, b0 = G.field_storage(e0, False), G.field_storage(b0, False)
+    st = G.oracle_state(dims, w["n_x"], w["rho0"], w["dt"])
+    G.start(s, st, parts, e=e0, b=b0)
+    del st
+    _full_size_check(s, dims, w["dt"], w["n_x"], w["rho0"], G.PAIR, parts, e0, b0, 2,
+                     2.0 / (w["n_x"] ** 2 * w["rho0"]) * 2 * w["ppc_per_beam"])
+    s.close()
+
+
+@pytest.mark.slow
+def test_full_size_harris_512x256x4():
+    w = dict(W.HARRIS)
+    dims = w["dims"]
+    species, b, loads, _, _ = G.harris_setup(w)
+    from oracle import oracle as O
+    xs, ua, ub = [], [], []
+    for ld in loads:
+        x, a, bb = O.load_pairs(dims, ld["seed"], ld["stream"], ld["npairs"], ld["A"], ld["B"],
+                                **ld.get("prof", {}))
+        xs.append(x)
+        ua.append(a)
+        ub.append(bb)
+    x = np.concatenate(xs)
+    n = len(x)
+    s = G.sim(dims, w["n_x"], w["rho0"], [n, n], dt=w["dt"], sort_interval=50, species=species)
+    parts = [G.to_storage(x, np.concatenate(ua), dims, False), G.to_storage(x, np.concatenate(ub), dims, False)]
+    e0, b0 = np.zeros(3 * int(np.prod(dims))), G.field_storage(b, False)
+    st = G.oracle_state(dims, w["n_x"], w["rho0"], w["dt"], species=species)
+    G.start(s, st, parts, e=e0, b=b0)
+    del st
+    _full_size_check(s, dims, w["dt"], w["n_x"], w["rho0"], species, parts, e0, b0, 3,
+                     2.0 / (w["n_x"] ** 2 * w["rho0"]) * w["ppc"])
+    s.close()

@@ -35,8 +35,9 @@
  * word that the next pic_diag or pic_sync reports as PIC_EFLAG.
  *
  * Limits: n[0], n[1] <= 2048, n[2] <= 1024; tile edges are powers of two
- * between 1 and 8; at most PIC_MAX_SPECIES species; fewer than 2^31 particles
- * per species per box; dt < 1/sqrt(3) (3-D Courant bound of the Yee scheme).
+ * between 1 and 8; at most PIC_MAX_SPECIES species; fewer than 2^29 particle
+ * slots (capacity x headroom, plus 32 per tile and the overflow region) per
+ * species per box; dt < 1/sqrt(3) (3-D Courant bound of the Yee scheme).
  */
 #ifndef PIC_H
 #define PIC_H

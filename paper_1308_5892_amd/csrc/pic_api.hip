@@ -139,7 +139,8 @@ static int validate(const pic_config *cfg, std::vector<BoxHost> &bh, std::string
             if (mp < 0) { err = "negative capacity"; return PIC_EINVAL; }
             const int64_t ovf = std::max<int64_t>(1024, mp / 16);
             const int64_t slots = (int64_t)std::ceil(mp * hr) + 32 * (int64_t)H.ntiles + ovf;
-            if (slots >= (int64_t)1 << 31) { err = "more than 2^31 particle slots in one species"; return PIC_EINVAL; }
+            // particle arrays are addressed with 32-bit byte offsets (8-byte elements in the FP64 form)
+            if (slots >= (int64_t)1 << 29) { err = "more than 2^29 particle slots in one species"; return PIC_EINVAL; }
             H.slots[s] = (int32_t)slots;
             H.ovf_cap[s] = (int32_t)ovf;
             H.stage_cap[s] = (int32_t)std::max<int64_t>(mp, 1);

@@ -217,13 +217,23 @@ __device__ inline int claim_slot(PIC_GLOBAL int32_t *cnt, int target, bool pendi
     return slot;
 }
 
+// Element i of a particle array as a 32-bit byte offset from the array's
+// (wave-uniform) base: slot counts stay below 2^29, so the offset fits and the
+// access is one scalar base plus one vector offset.
+template <typename T>
+__device__ inline PIC_GLOBAL T &slot_ref(PIC_GLOBAL T *base, int i)
+{
+    return *reinterpret_cast<PIC_GLOBAL T *>(reinterpret_cast<PIC_GLOBAL char *>(base) +
+                                             (uint32_t)i * (uint32_t)sizeof(T));
+}
+
 template <typename R>
 __device__ inline void write_particle(const PBuf<R> &P, int at, int32_t cell, const R d[3], const R u[3], int32_t id)
 {
-    P.cell[at] = cell;
-    P.d[0][at] = d[0]; P.d[1][at] = d[1]; P.d[2][at] = d[2];
-    P.u[0][at] = u[0]; P.u[1][at] = u[1]; P.u[2][at] = u[2];
-    if (P.id) P.id[at] = id;
+    slot_ref(P.cell, at) = cell;
+    slot_ref(P.d[0], at) = d[0]; slot_ref(P.d[1], at) = d[1]; slot_ref(P.d[2], at) = d[2];
+    slot_ref(P.u[0], at) = u[0]; slot_ref(P.u[1], at) = u[1]; slot_ref(P.u[2], at) = u[2];
+    if (P.id) slot_ref(P.id, at) = id;
 }
 
 // Slot of copy `dst` for position `pos` of the B range of tile `tgt`, or of the
@@ -269,6 +279,20 @@ __device__ inline TileRanges tile_ranges(const SpeciesDev<R> &S, int c, int T)
     r.na = S.na[c][T];
     r.bs = S.bs[c][T];
     r.n = r.na + max(0, min(S.nb[c][T], S.seg_cap[c][T] - r.bs));
+    return r;
+}
+
+// The same for a tile index that is uniform over the wave: the values are
+// kept in scalar registers.
+template <typename R>
+__device__ inline TileRanges tile_ranges_uniform(const SpeciesDev<R> &S, int c, int T)
+{
+    const TileRanges v = tile_ranges(S, c, T);
+    TileRanges r;
+    r.start = __builtin_amdgcn_readfirstlane(v.start);
+    r.na = __builtin_amdgcn_readfirstlane(v.na);
+    r.bs = __builtin_amdgcn_readfirstlane(v.bs);
+    r.n = __builtin_amdgcn_readfirstlane(v.n);
     return r;
 }
 
@@ -347,6 +371,11 @@ __host__ __device__ inline size_t queue_bytes()
 // Bytes of dynamic LDS for a tile with edges (t0, t1, t2): the trilinear
 // coefficients of every cell (48 values), the piece queues, then a region that
 // first holds the staged raw fields and node fields and then the tile current.
+// Values per cell in the gather's coefficient table: 8 per field component,
+// padded from 48 to 52 so that the 16-byte reads of lanes in different cells
+// start on different LDS banks.
+constexpr int kCoef = 52;
+
 template <typename R>
 __host__ __device__ inline size_t tile_lds_bytes(int t0, int t1, int t2)
 {
@@ -357,7 +386,7 @@ __host__ __device__ inline size_t tile_lds_bytes(int t0, int t1, int t2)
     const size_t raw = (3 * (jn + bn) + 6 * nn) * sizeof(R);
     const size_t jb = 3 * jn * sizeof(typename JType<R>::T);
     const size_t u = raw > jb ? raw : jb;
-    return nc * 48 * sizeof(R) + queue_bytes<R>() + ((u + 15) & ~size_t(15));
+    return nc * kCoef * sizeof(R) + queue_bytes<R>() + ((u + 15) & ~size_t(15));
 }
 
 // q / m for 0 <= q < 4096 and 1 <= m <= 16, with mul = 65536 / m + 1: the
@@ -536,7 +565,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     // LDS: per-cell trilinear coefficients | piece queues | union of {raw e,
     // raw b, node fields} (set-up) and the tile current (particle loop)
     const int tsx = B.tshift[0], tsxy = B.tshift[0] + B.tshift[1];
-    const int ncoef = 48 << (B.tshift[0] + B.tshift[1] + B.tshift[2]);
+    const int ncoef = kCoef << (B.tshift[0] + B.tshift[1] + B.tshift[2]);
     R *coef = reinterpret_cast<R *>(smem);
     unsigned char *qmem = smem + (((size_t)ncoef * sizeof(R) + 15) & ~size_t(15));
     unsigned char *uni = qmem + queue_bytes<R>();
@@ -555,7 +584,6 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         sh_back[tid] = 0;
     }
     if (tid < kMaxSpecies * 27) (&sh_bin[0][0])[tid] = 0;
-    int nsp_n[kMaxSpecies];
 
     // region indices are decoded by multiply-shift (edges of at most 11 and
     // fewer than 2^11 points: exact)
@@ -638,7 +666,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         for (int q = tid; q < ncell; q += kBlock) {
             const int jk = div_small(q, mEX), i = q - jk * g.ext[0];
             const int k = div_small(jk, mEY), j = jk - k * g.ext[1];
-            R *cf = coef + 48 * (i | (j << tsx) | (k << tsxy));
+            R *cf = coef + kCoef * (i | (j << tsx) | (k << tsxy));
             const int m = i + NX * j + NXY * k;
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
@@ -705,14 +733,13 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     for (int s = 0; s < C.nsp; ++s) {
         const SpeciesDev<R> &S = B.sp[s];
         const PBuf<R> &P = S.buf[C.cur];
-        const TileRanges src = tile_ranges(S, C.cur, T);
+        const TileRanges src = tile_ranges_uniform(S, C.cur, T);
         const int n = src.n;
-        nsp_n[s] = n;
         const R hk = R(0.5) * C.kq[s] * C.dt;
         const R scale = -C.qs[s] * qscale_bits<R>();
         const int32_t sgnbit = scale < R(0) ? (int32_t)0x80000000 : 0;
         const int dst = C.cur ^ 1;
-        const int dst_start = S.seg_start[dst][T];
+        const int dst_start = __builtin_amdgcn_readfirstlane(S.seg_start[dst][T]);
         // the particle of the next iteration is loaded one iteration ahead, so
         // that its HBM latency is covered by the work on the current one
         const int32_t cell_pad = pack_cell(g.o[0], g.o[1], g.o[2]);
@@ -721,10 +748,10 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         auto fetch = [&](int q) {
             if (q < n) {
                 const int at = src.slot(q);
-                nx_cell = P.cell[at];
-                nx_d[0] = P.d[0][at]; nx_d[1] = P.d[1][at]; nx_d[2] = P.d[2][at];
-                nx_u[0] = P.u[0][at]; nx_u[1] = P.u[1][at]; nx_u[2] = P.u[2][at];
-                if (P.id) nx_id = P.id[at];
+                nx_cell = slot_ref(P.cell, at);
+                nx_d[0] = slot_ref(P.d[0], at); nx_d[1] = slot_ref(P.d[1], at); nx_d[2] = slot_ref(P.d[2], at);
+                nx_u[0] = slot_ref(P.u[0], at); nx_u[1] = slot_ref(P.u[1], at); nx_u[2] = slot_ref(P.u[2], at);
+                if (P.id) nx_id = slot_ref(P.id, at);
             } else {
                 nx_cell = cell_pad;
                 nx_d[0] = nx_d[1] = nx_d[2] = R(0.5);
@@ -750,7 +777,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             if (!inside) {
                 gather_global(B, ix, iy, iz, d, hdt, E, Bf);
             } else {
-                const R *cf = coef + 48 * (lx | (ly << tsx) | (lz << tsxy));
+                const R *cf = coef + kCoef * (lx | (ly << tsx) | (lz << tsxy));
                 const R pxy = d[0] * d[1], pyz = d[1] * d[2], pzx = d[2] * d[0], pxyz = pxy * d[2];
                 R F[6];
 #pragma unroll
@@ -926,13 +953,13 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         const SpeciesDev<R> &S = B.sp[s];
         const PBuf<R> &Q = S.buf[dst];
         const int nl = sh_back[s];
-        const int first = S.seg_start[dst][T] + nsp_n[s] - nl;   // staged leavers [first, first + nl)
+        const int first = S.seg_start[dst][T] + tile_ranges(S, C.cur, T).n - nl;   // staged leavers [first, first + nl)
         for (int q = tid; q < nl; q += kBlock) {
             const int from = first + q;
-            const int32_t cell = Q.cell[from];
-            const R d[3] = {Q.d[0][from], Q.d[1][from], Q.d[2][from]};
-            const R u[3] = {Q.u[0][from], Q.u[1][from], Q.u[2][from]};
-            const int32_t id = Q.id ? Q.id[from] : 0;
+            const int32_t cell = slot_ref(Q.cell, from);
+            const R d[3] = {slot_ref(Q.d[0], from), slot_ref(Q.d[1], from), slot_ref(Q.d[2], from)};
+            const R u[3] = {slot_ref(Q.u[0], from), slot_ref(Q.u[1], from), slot_ref(Q.u[2], from)};
+            const int32_t id = Q.id ? slot_ref(Q.id, from) : 0;
             const int c3[3] = {cell_x(cell), cell_y(cell), cell_z(cell)};
             const int k = move_bin(g, rim, c3);         // the same bin as at staging
             const int tn = neighbor_tile(B, g, k);      // the tile whose range was claimed

@@ -356,16 +356,19 @@ __device__ inline TileGeom<R> tile_geom(const BoxDev<R> &B, int T)
     return g;
 }
 
-// Per-wave queue of deposit pieces (LDS ring buffer): the pieces of a move
-// after the first one (cell-crossing moves) wait here and are deposited 64 at
-// a time by the whole wave.
+// Per-wave queue of unfinished moves (LDS ring buffer): a move that crosses
+// node planes deposits its first piece at once and waits here for the rest;
+// the wave deposits the next piece of 64 queued moves at a time and puts back
+// those that still have pieces left.  An entry holds the move (start offsets
+// and displacement), the LDS index of its home cell with the species sign, and
+// its crossing order, piece count and next piece.
 constexpr int kQCap = 128;
 constexpr int kWaves = kBlock / 64;
 
 template <typename R>
 __host__ __device__ inline size_t queue_bytes()
 {
-    return (size_t)kWaves * kQCap * (sizeof(int32_t) + 6 * sizeof(R));
+    return (size_t)kWaves * kQCap * (2 * sizeof(int32_t) + 6 * sizeof(R));
 }
 
 // Bytes of dynamic LDS for a tile with edges (t0, t1, t2): the trilinear
@@ -376,17 +379,36 @@ __host__ __device__ inline size_t queue_bytes()
 // start on different LDS banks.
 constexpr int kCoef = 52;
 
+// LDS of one push block for tiles of t0 x t1 x t2 cells, three regions:
+//   [coef]   the gather's coefficient table (kCoef values per cell);
+//   [stage]  the piece queues during the particle loop, the staged raw e and
+//            b (tile plus halo) during set-up;
+//   [union]  the node fields during set-up, the tile current afterwards.
+struct TileLds {
+    size_t coef, stage, uni;
+    __host__ __device__ size_t total() const { return coef + stage + uni; }
+};
+
 template <typename R>
-__host__ __device__ inline size_t tile_lds_bytes(int t0, int t1, int t2)
+__host__ __device__ inline TileLds tile_lds(int t0, int t1, int t2)
 {
     const size_t nc = (size_t)t0 * t1 * t2;
     const size_t nn = (size_t)(t0 + 1) * (t1 + 1) * (t2 + 1);
     const size_t jn = (size_t)(t0 + 3) * (t1 + 3) * (t2 + 3);
     const size_t bn = (size_t)(t0 + 2) * (t1 + 2) * (t2 + 2);
-    const size_t raw = (3 * (jn + bn) + 6 * nn) * sizeof(R);
-    const size_t jb = 3 * jn * sizeof(typename JType<R>::T);
-    const size_t u = raw > jb ? raw : jb;
-    return nc * kCoef * sizeof(R) + queue_bytes<R>() + ((u + 15) & ~size_t(15));
+    const size_t raw = 3 * (jn + bn) * sizeof(R), q = queue_bytes<R>();
+    const size_t nodes = 6 * nn * sizeof(R), jb = 3 * jn * sizeof(typename JType<R>::T);
+    TileLds L;
+    L.coef = (nc * kCoef * sizeof(R) + 15) & ~size_t(15);
+    L.stage = ((raw > q ? raw : q) + 15) & ~size_t(15);
+    L.uni = ((nodes > jb ? nodes : jb) + 15) & ~size_t(15);
+    return L;
+}
+
+template <typename R>
+__host__ __device__ inline size_t tile_lds_bytes(int t0, int t1, int t2)
+{
+    return tile_lds<R>(t0, t1, t2).total();
 }
 
 // q / m for 0 <= q < 4096 and 1 <= m <= 16, with mul = 65536 / m + 1: the
@@ -427,6 +449,36 @@ __device__ inline void deposit_piece(typename JType<R>::T *jl, int cb, const int
 
 template <typename R>
 __device__ inline R sel3(int i, R a0, R a1, R a2) { return i == 0 ? a0 : (i == 1 ? a1 : a2); }
+
+// Node planes crossed by the move d -> x1 = d + D in the home-cell frame
+// (|D| < 1: at most one per axis): direction per axis and the crossing
+// parameter lambda in (0, 1] (2 where no plane is crossed).
+template <typename R>
+__device__ inline void move_crossings(const R d[3], const R D[3], R x1[3], int dir[3], R lam[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        x1[a] = d[a] + D[a];
+        dir[a] = x1[a] < R(0) ? -1 : (x1[a] >= R(1) ? 1 : 0);
+        lam[a] = dir[a] != 0 ? ((dir[a] > 0 ? R(1) : R(0)) - d[a]) * fast_rcp(D[a]) : R(2);
+    }
+}
+
+// Point where axis `ax` meets its plane (parameter l): that coordinate is the
+// plane itself, every other coordinate stays on its own side of its plane
+// (the far side once its own crossing parameter is <= l).
+template <typename R>
+__device__ inline void crossing_point(const R d[3], const R D[3], const int dir[3], const R lam[3], int ax, R l,
+                                      R q[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        R v = fma(l, D[a], d[a]);
+        if (dir[a] > 0) v = lam[a] <= l ? fmax(v, R(1)) : fmin(v, R(1));
+        else if (dir[a] < 0) v = lam[a] <= l ? fmin(v, R(0)) : fmax(v, R(0));
+        q[a] = a == ax ? (dir[a] > 0 ? R(1) : R(0)) : v;
+    }
+}
 
 // Tile one step away from tile T in direction code = (dx+1) + 3(dy+1) + 9(dz+1).
 template <typename R>
@@ -565,14 +617,14 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     // LDS: per-cell trilinear coefficients | piece queues | union of {raw e,
     // raw b, node fields} (set-up) and the tile current (particle loop)
     const int tsx = B.tshift[0], tsxy = B.tshift[0] + B.tshift[1];
-    const int ncoef = kCoef << (B.tshift[0] + B.tshift[1] + B.tshift[2]);
+    const TileLds lds = tile_lds<R>(1 << B.tshift[0], 1 << B.tshift[1], 1 << B.tshift[2]);
     R *coef = reinterpret_cast<R *>(smem);
-    unsigned char *qmem = smem + (((size_t)ncoef * sizeof(R) + 15) & ~size_t(15));
-    unsigned char *uni = qmem + queue_bytes<R>();
-    R *re = reinterpret_cast<R *>(uni);          // raw e, 3 x JN, origin o-1
-    R *rb = re + 3 * g.JN;                        // raw b, 3 x BN, origin o-1
-    R *node = rb + 3 * g.BN;                      // node fields, 6 x NN, origin o
-    JT *jl = reinterpret_cast<JT *>(uni);         // J, 3 x JN, origin o-1 (after set-up)
+    unsigned char *qmem = smem + lds.coef;
+    unsigned char *uni = qmem + lds.stage;
+    R *re = reinterpret_cast<R *>(qmem);          // raw e, 3 x JN, origin o-1 (set-up)
+    R *rb = re + 3 * g.JN;                        // raw b, 3 x BN, origin o-1 (set-up)
+    R *node = reinterpret_cast<R *>(uni);         // node fields, 6 x NN, origin o (set-up)
+    JT *jl = reinterpret_cast<JT *>(uni);         // J, 3 x JN, origin o-1 (particle loop)
 
     // re-binning counters: per species the stayers (from the front of the
     // tile's new A range), the leavers (staged from the back) and the leavers
@@ -704,31 +756,75 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             joff[a][3] = a * g.JN + S[b1] + S[b2];
         }
     }
-    // this wave's piece queue: packed cell index (sign bit = species sign), start, displacement
+    // this wave's queue of unfinished moves: home-cell index (sign bit =
+    // species sign), meta = next piece | pieces << 2 | crossing order << 4,
+    // start offsets d and displacement D
     const int wave = tid >> 6, lane = __lane_id();
     int32_t *qidx = reinterpret_cast<int32_t *>(qmem) + wave * kQCap;
-    R *qval = reinterpret_cast<R *>(qmem + kWaves * kQCap * sizeof(int32_t)) + wave * 6 * kQCap;
+    int32_t *qmeta = reinterpret_cast<int32_t *>(qmem) + (kWaves + wave) * kQCap;
+    R *qval = reinterpret_cast<R *>(qmem + 2 * kWaves * kQCap * sizeof(int32_t)) + wave * 6 * kQCap;
     int qhead = 0, qcount = 0;                    // wave-uniform
     const uint64_t lt = lanemask_lt();
-    auto drain = [&](int limit) {                 // deposit up to `limit` queued pieces (whole wave)
+    auto put = [&](bool has, int32_t w, int32_t meta, const R d[3], const R D[3]) {
+        const uint64_t mh = __ballot(has);
+        if (has) {
+            const int pos = (qhead + qcount + (int)__popcll(mh & lt)) & (kQCap - 1);
+            qidx[pos] = w;
+            qmeta[pos] = meta;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                qval[a * kQCap + pos] = d[a];
+                qval[(3 + a) * kQCap + pos] = D[a];
+            }
+        }
+        qcount += (int)__popcll(mh);
+    };
+    // deposit the next piece of up to 64 queued moves (whole wave); moves with
+    // pieces left go back into the queue
+    auto drain = [&]() {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int nq = min(qcount, limit);
+        const int nq = min(qcount, 64);
+        int32_t w = 0, meta = 0;
+        R d[3] = {R(0), R(0), R(0)}, D[3] = {R(0), R(0), R(0)};
         if (lane < nq) {
             const int e = (qhead + lane) & (kQCap - 1);
-            const int32_t w = qidx[e];
-            R ps[3], pd[3];
+            w = qidx[e];
+            meta = qmeta[e];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) { ps[a] = qval[a * kQCap + e]; pd[a] = qval[(3 + a) * kQCap + e]; }
-            const R sc = w < 0 ? -qscale_bits<R>() : qscale_bits<R>();
-            deposit_piece<R>(jl, w & 0x7fffffff, joff, ps, pd, sc);
+            for (int a = 0; a < 3; ++a) { d[a] = qval[a * kQCap + e]; D[a] = qval[(3 + a) * kQCap + e]; }
         }
         qhead = (qhead + nq) & (kQCap - 1);
         qcount -= nq;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int k = meta & 3, nb = (meta >> 2) & 3;
+        bool more = false;
+        if (lane < nq) {
+            R x1[3], lam[3];
+            int dir[3];
+            move_crossings(d, D, x1, dir, lam);
+            const int oa = (meta >> (2 + 2 * k)) & 3, ob = (meta >> (4 + 2 * k)) & 3;   // axes of crossings k, k+1
+            R ps[3], pe[3];
+            crossing_point(d, D, dir, lam, oa, sel3(oa, lam[0], lam[1], lam[2]), ps);
+            if (k < nb) crossing_point(d, D, dir, lam, ob, sel3(ob, lam[0], lam[1], lam[2]), pe);
+            else { pe[0] = x1[0]; pe[1] = x1[1]; pe[2] = x1[2]; }
+            int offc[3];
+            R sv[3], dd[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                offc[a] = (int)floor(R(0.5) * (ps[a] + pe[a]));   // cell of the piece
+                sv[a] = ps[a] - R(offc[a]);
+                dd[a] = pe[a] - ps[a];
+            }
+            const int cb = (w & 0x7fffffff) + offc[0] + __mul24(JX, offc[1]) + __mul24(JXY, offc[2]);
+            const R sc = w < 0 ? -qscale_bits<R>() : qscale_bits<R>();
+            deposit_piece<R>(jl, cb, joff, sv, dd, sc);
+            more = k < nb;
+        }
+        put(more, w, meta + 1, d, D);
     };
     for (int s = 0; s < C.nsp; ++s) {
         const SpeciesDev<R> &S = B.sp[s];
@@ -795,35 +891,24 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                 u[0] = u[1] = u[2] = R(0);
             }
             const R ig = C.dt * fast_rsqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            const R D[3] = {ig * u[0], ig * u[1], ig * u[2]};
+            R D[3] = {ig * u[0], ig * u[1], ig * u[2]};
+            // D stays the rounded product (no multiply-add into x1 = d + D):
+            // a queued move's crossings are recomputed from the stored (d, D)
+            // and must come out identical
+#pragma unroll
+            for (int a = 0; a < 3; ++a) asm volatile("" : "+v"(D[a]));
 
-            // node planes crossed by the move (|D| < 1: at most one per axis),
-            // their crossing parameters in increasing order
+            // node planes crossed by the move and their crossing parameters
+            // in increasing order (axes o0, o1, o2)
             R x1[3], lam[3];
             int dir[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                x1[a] = d[a] + D[a];
-                dir[a] = x1[a] < R(0) ? -1 : (x1[a] >= R(1) ? 1 : 0);
-                lam[a] = dir[a] != 0 ? ((dir[a] > 0 ? R(1) : R(0)) - d[a]) * fast_rcp(D[a]) : R(2);
-            }
+            move_crossings(d, D, x1, dir, lam);
             const int nb = (dir[0] != 0) + (dir[1] != 0) + (dir[2] != 0);
             int o0 = 0, o1 = 1, o2 = 2;
             R l0 = lam[0], l1 = lam[1], l2 = lam[2];
             if (l1 < l0) { R t = l0; l0 = l1; l1 = t; int q = o0; o0 = o1; o1 = q; }
             if (l2 < l1) { R t = l1; l1 = l2; l2 = t; int q = o1; o1 = o2; o2 = q; }
             if (l1 < l0) { R t = l0; l0 = l1; l1 = t; int q = o0; o0 = o1; o1 = q; }
-            // breakpoint where axis ax (parameter l) meets its plane; the other
-            // coordinates stay on their own side of their planes
-            auto breakpoint = [&](int ax, R l, R q[3]) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    R v = d[a] + l * D[a];
-                    if (dir[a] > 0) v = lam[a] <= l ? fmax(v, R(1)) : fmin(v, R(1));
-                    else if (dir[a] < 0) v = lam[a] <= l ? fmin(v, R(0)) : fmax(v, R(0));
-                    q[a] = a == ax ? (dir[a] > 0 ? R(1) : R(0)) : v;
-                }
-            };
 
             // new cell and offset, re-binning target, and the slot claims:
             // the stayers' block of slots by one returning atomic of their
@@ -872,14 +957,14 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             }
             if (at >= 0) write_particle(S.buf[dst], at, ncell, dn, u, id);
 
-            // deposit: the first piece (in the home cell) at once, later pieces
-            // through the wave's queue
+            // deposit: the first piece (in the home cell) at once, the move
+            // into the wave's queue for its later pieces
             const int jb = (lx + 1) + __mul24(JX, ly + 1) + __mul24(JXY, lz + 1);
             R p1[3];
             if (nb == 0) {
                 p1[0] = x1[0]; p1[1] = x1[1]; p1[2] = x1[2];
             } else {
-                breakpoint(o0, l0, p1);
+                crossing_point(d, D, dir, lam, o0, l0, p1);
             }
             if (valid && inside) {
                 const R dd[3] = {p1[0] - d[0], p1[1] - d[1], p1[2] - d[2]};
@@ -893,36 +978,11 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                                       quantize(v));
                 });
             }
-            R ps[3] = {p1[0], p1[1], p1[2]};
-#pragma unroll
-            for (int k = 1; k <= 3; ++k) {
-                const bool has = valid && inside && k <= nb;
-                const uint64_t mh = __ballot(has);
-                if (mh == 0ull) break;
-                R pe[3];
-                if (k < nb) breakpoint(k == 1 ? o1 : o2, k == 1 ? l1 : l2, pe);
-                else { pe[0] = x1[0]; pe[1] = x1[1]; pe[2] = x1[2]; }
-                if (has) {
-                    const int pos = (qhead + qcount + (int)__popcll(mh & lt)) & (kQCap - 1);
-                    int offc[3];
-                    R sv[3];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        offc[a] = (int)floor(R(0.5) * (ps[a] + pe[a]));   // cell of the piece
-                        sv[a] = ps[a] - R(offc[a]);
-                        qval[(3 + a) * kQCap + pos] = pe[a] - ps[a];
-                        qval[a * kQCap + pos] = sv[a];
-                    }
-                    qidx[pos] = (jb + offc[0] + __mul24(JX, offc[1]) + __mul24(JXY, offc[2])) | sgnbit;
-                }
-                qcount += (int)__popcll(mh);
-                ps[0] = pe[0]; ps[1] = pe[1]; ps[2] = pe[2];
-                if (qcount >= 64) drain(64);
-            }
-
+            put(valid && inside && nb > 0, jb | sgnbit, 1 | (nb << 2) | (o0 << 4) | (o1 << 6) | (o2 << 8), d, D);
+            while (qcount >= 64) drain();
         }
     }
-    while (qcount > 0) drain(64);
+    while (qcount > 0) drain();
     __syncthreads();
 
     // 6. flush the tile current to HBM (integer sums: order-independent)

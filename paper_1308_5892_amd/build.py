@@ -1,7 +1,8 @@
 """Build libpic.so (the gfx950 HIP library behind include/pic.h) in-tree.
 
 Each .hip source is compiled for gfx950 only; packed FP32 instructions are
-disabled for the whole library (-packed-fp32-ops).
+disabled for the whole library (-packed-fp32-ops), and so is the compiler's
+wave-level atomic rewrite.
 """
 from __future__ import annotations
 
@@ -20,6 +21,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # atomics here are already aggregated per wave where that pays (slot claims,
+    # counters); the compiler's own wave-level rewrite only adds instructions
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-I" + INCLUDE, "-I" + CSRC,
 ]
 

@@ -23,9 +23,15 @@ template <typename R> __device__ inline R qscale_bits();
 template <> __device__ inline float qscale_bits<float>() { return 2147483648.0f; }  // 2^31
 template <> __device__ inline double qscale_bits<double>() { return 1.0; }
 
-// FP32 form: a value already scaled by 2^31 rounded to the nearest integer
-// (|value| < 2^31 since every face value of one move is below one cell volume)
-__device__ inline int quantize(float v) { return __float2int_rn(v); }
+// FP32 form: a value already scaled by 2^31 rounded to the nearest integer,
+// ties upward, in one conversion (|value| < 2^31 since every face value of one
+// move is below one cell volume)
+__device__ inline int quantize(float v)
+{
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
 __device__ inline double quantize(double v) { return v; }
 
 __device__ inline void atomic_add_lds(long long *p, long long v)
@@ -437,7 +443,7 @@ __device__ inline void deposit_piece(typename JType<R>::T *jl, int cb, const int
         const int b1 = a == 2 ? 0 : a + 1, b2 = a == 0 ? 2 : a - 1;
         const R PK = m[b1] * m[b2] + dd[b1] * dd[b2] * R(1.0 / 12.0);
         const R F = scale * dd[a];
-        const R t11 = F * PK, t01 = F * (m[b2] - PK), t10 = F * (m[b1] - PK);
+        const R t11 = F * PK, t01 = fma(F, m[b2], -t11), t10 = fma(F, m[b1], -t11);
         const auto q11 = quantize(t11), q01 = quantize(t01), q10 = quantize(t10);
         const auto q00 = quantize(F) - q01 - q10 - q11;
         atomic_add_lds(&jl[cb + off[a][0]], q00);

@@ -2,10 +2,13 @@
 """Benchmark of the PIC hot path on one MI355X: particle pushes per second.
 
 One step is the full leap-frog cycle (fused gather + Boris push + deposit per
-tile, Yee updates of b and e, periodic counting-sort repacks) over the thermal
-pair plasma workload: 64^3 cells, 64 pairs per cell (33.5 M particles),
-theta = 0.1, dt = 0.5, n_x = 10, uniform density, synthetic seeded inputs that
-stand in for the paper's thermal test problems.
+tile, Yee updates of b and e, periodic counting-sort repacks).  The headline
+workload (the default) is the thermal pair plasma: 64^3 cells, 64 pairs per
+cell (33.5 M particles), theta = 0.1, dt = 0.5, n_x = 10.  --workload selects
+one of the other families instead: counter-streaming beams 256x256x4, the
+double Harris sheet 512x256x4, or the ensemble of 256 boxes in one launch.
+All inputs are synthetic and seeded; they stand in for the paper's thermal,
+beam and current-sheet test problems.
 
 Prints ONE JSON line.  Besides the headline value it carries:
   roofline      the push kernel's algorithmic HBM bytes per launch divided by
@@ -14,8 +17,8 @@ Prints ONE JSON line.  Besides the headline value it carries:
                 traffic is the counter-measured HBM bytes per launch
                 (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy) when the
                 committed counter summary matches the current kernel source;
-  cpu_baseline  the FP64 CPU oracle timed on a bounded sample of the same
-                workload on this host;
+  cpu_baseline  the FP64 CPU oracle timed on a bounded sample of the thermal
+                workload on this host (thermal workload only);
   fp64_form     the same workload in the FP64 GPU form, and the speedup.
 """
 from __future__ import annotations
@@ -23,6 +26,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -32,7 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle pushes/s (gather+push+deposit) at 1 GPU; % HBM roofline vs FP64 form"
 HBM_PEAK_GBS = 8000.0
-PMC_FILE = os.path.join(ROOT, "profiles", "push_kernel_thermal64_pmc.txt")
+PMC_FILE = os.path.join(ROOT, "profiles", "push_kernel_{}_pmc.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1308_5892_amd", "csrc", "pic_kernels.hip")
 
 
@@ -44,13 +48,14 @@ def kernel_sha():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def pmc_traffic():
+def pmc_traffic(workload):
     """Counter-based HBM bytes per push launch from the committed summary, or
     None when it is missing or was taken on another version of the kernel."""
-    if not os.path.exists(PMC_FILE):
+    path = PMC_FILE.format(workload)
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(PMC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
@@ -62,22 +67,104 @@ def pmc_traffic():
         return None
 
 
-def make_sim(w, fp64, tile, sort_interval):
+def harris_parameters(w):
+    """Relativistic Harris equilibrium (App. C) for the sheet workload: current
+    sheet half-thickness L in cells and b0 = omega_ce in code units, from the
+    electron temperature, the electron drift Gamma_e U_e / c, chi and the mass
+    ratio; d_e = n_x cells at the peak density."""
+    r = math.sqrt(4.0 * w["chi"] * w["theta_e"])              # omega_ce / omega'_pe
+    gamma = math.sqrt(1.0 + w["gu_e"] ** 2)
+    L_de = 2.0 * w["theta_e"] / (r * w["gu_e"]) * math.sqrt(gamma)
+    return {"L": L_de * w["n_x"], "b0": r / math.sqrt(gamma) / w["n_x"],
+            "theta_i": (2.0 * w["chi"] - 1.0) * w["theta_e"] / w["mass_ratio"],
+            "gu_i": (2.0 * w["chi"] - 1.0) * w["gu_e"]}
+
+
+def workload(name, tile):
+    """Boxes, species, dt, loads (pic_load_desc list) and Harris fields of one
+    workload family, with every box on the given tile shape."""
     from paper_1308_5892_amd import pic as P
-    cells = w["dims"][0] * w["dims"][1] * w["dims"][2]
-    npairs = w["ppc"] * cells
-    box = {"n": w["dims"], "n_x": w["n_x"], "rho0": 2.0 * w["ppc"], "max_particles": [npairs, npairs],
-           "tile": tile}
-    sim = P.Simulation([box], [(-1.0, 1.0), (1.0, 1.0)], w["dt"], fp64=fp64, sort_interval=sort_interval)
-    sim.load(0, 0, 1, (w["theta"], 0.0, 1), (w["theta"], 0.0, 1), w["ppc"], seed=w["seed"])
+    import pic_inputs as W
+    pair = [(-1.0, 1.0), (1.0, 1.0)]
+    harris = []
+    if name == "thermal64":
+        w = W.THERMAL64
+        cells = w["dims"][0] * w["dims"][1] * w["dims"][2]
+        npairs = w["ppc"] * cells
+        boxes = [{"n": w["dims"], "n_x": w["n_x"], "rho0": 2.0 * w["ppc"], "max_particles": [npairs, npairs],
+                  "tile": tile}]
+        species, dt = pair, w["dt"]
+        loads = [P.load_desc(0, 0, 1, (w["theta"], 0.0, 1), (w["theta"], 0.0, 1), w["ppc"], seed=w["seed"])]
+    elif name == "beams":
+        w = W.FILAMENT
+        cells = w["dims"][0] * w["dims"][1] * w["dims"][2]
+        npairs = 2 * w["ppc_per_beam"] * cells
+        boxes = [{"n": w["dims"], "n_x": w["n_x"], "rho0": w["rho0"], "max_particles": [npairs, npairs],
+                  "tile": tile}]
+        species, dt = pair, w["dt"]
+        gb = math.sqrt(w["gamma"] ** 2 - 1.0)
+        loads = [P.load_desc(0, 0, 1, (w["theta"], sg * gb, 0), (w["theta"], sg * gb, 0), w["ppc_per_beam"],
+                             seed=w["seed"], stream=k) for k, sg in ((0, 1.0), (1, -1.0))]
+    elif name == "harris":
+        w = W.HARRIS
+        hp = harris_parameters(w)
+        nx, ny, nz = w["dims"]
+        cells = nx * ny * nz
+        L, hw = hp["L"], nx / 4.0
+        n_sheet = round(w["ppc"] * (cells / nx) * 2 * L * math.tanh(hw / L))
+        npairs = 2 * n_sheet + round(w["background"] * w["ppc"] * cells)
+        boxes = [{"n": w["dims"], "n_x": w["n_x"], "rho0": w["rho0"], "max_particles": [npairs + 64] * 2,
+                  "tile": tile}]
+        species, dt = [(-1.0, 1.0), (1.0, w["mass_ratio"])], w["dt"]
+        harris = [(0, 0, 1, hp["b0"], L, [nx / 4.0, 3.0 * nx / 4.0])]
+        loads = [P.load_desc(0, 0, 1, (w["theta_e"], -sg * w["gu_e"], 2), (hp["theta_i"], sg * hp["gu_i"], 2),
+                             w["ppc"], seed=w["seed"], stream=k, profile=1, profile_axis=0, centre=c, thickness=L,
+                             half_width=hw)
+                 for k, (c, sg) in enumerate(((nx / 4.0, 1.0), (3.0 * nx / 4.0, -1.0)))]
+        loads.append(P.load_desc(0, 0, 1, (w["theta_e"], 0.0, 2), (hp["theta_i"], 0.0, 2),
+                                 w["background"] * w["ppc"], seed=w["seed"], stream=2))
+    elif name == "ensemble":
+        spec = W.ENSEMBLE
+        blist = W.ensemble_boxes(spec)
+        boxes = []
+        for bx in blist:
+            n = bx["dims"][0] * bx["dims"][1] * bx["dims"][2] * bx["ppc"]
+            boxes.append({"n": bx["dims"], "n_x": spec["n_x"], "rho0": 2.0 * bx["ppc"], "max_particles": [n, n],
+                          "tile": tile})
+        species, dt = pair, spec["dt"]
+        loads = [P.load_desc(i, 0, 1, (bx["theta"], 0.0, 1), (bx["theta"], 0.0, 1), bx["ppc"], seed=bx["seed"])
+                 for i, bx in enumerate(blist)]
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return {"boxes": boxes, "species": species, "dt": dt, "loads": loads, "harris": harris}
+
+
+def make_sim(wl, fp64, sort_interval):
+    """Build and load a workload; returns (sim, particles, cells)."""
+    from paper_1308_5892_amd import pic as P
+    sim = P.Simulation(wl["boxes"], wl["species"], wl["dt"], fp64=fp64, sort_interval=sort_interval)
+    for h in wl["harris"]:
+        sim.harris_field(*h)
+    for d in wl["loads"]:
+        P.pic_load_maxwell_juttner(sim.ctx, d)
     sim.step(0)  # bin the loaded pairs and integrate u back by dt/2
-    return sim, 2 * npairs, cells
+    npart = sum(int(sim.diag(i)["count"].sum()) for i in range(len(sim.boxes)))
+    ncell = sum(b["n"][0] * b["n"][1] * b["n"][2] for b in wl["boxes"])
+    return sim, npart, ncell
 
 
-def time_form(w, fp64, steps, warmup, tile, sort_interval):
+WORKLOAD_TEXT = {
+    "thermal64": "thermal pair plasma 64^3, 64 pairs/cell, theta=0.1, dt=0.5, n_x=10",
+    "beams": "counter-streaming pair beams 256x256x4, gamma=3 along +-x, 32 pairs/cell/beam, theta=0.01, n_x=20",
+    "harris": "double Harris sheet 512x256x4, m_i/m_e=25, theta_e=1, 64 pairs/cell at peak, background 0.1, n_x=15",
+    "ensemble": "ensemble of 256 periodic thermal boxes, edges 8..32, 4..256 pairs/cell, theta 0.05..1, n_x=10",
+}
+
+
+def time_form(wl, fp64, steps, warmup, sort_interval):
     import torch
     from paper_1308_5892_amd import pic as P
-    sim, npart, cells = make_sim(w, fp64, tile, sort_interval)
+    sim, npart, cells = make_sim(wl, fp64, sort_interval)
     torch.cuda.synchronize()
     if warmup:
         sim.step(warmup)
@@ -88,7 +175,13 @@ def time_form(w, fp64, steps, warmup, tile, sort_interval):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     tm = P.pic_get_timing(sim.ctx)
-    d = sim.diag(0)
+    ds = [sim.diag(i) for i in range(len(sim.boxes))]
+    d = {"flags": 0, "count": 0, "gauss_max": 0.0, "n_overflow": 0}
+    for x in ds:
+        d["flags"] |= x["flags"]
+        d["count"] += int(x["count"].sum())
+        d["n_overflow"] += int(x["n_overflow"].sum())
+        d["gauss_max"] = max(d["gauss_max"], x["gauss_max"])
     sim.close()
     return {"seconds": t1 - t0, "npart": npart, "cells": cells, "timing": tm, "diag": d}
 
@@ -130,6 +223,8 @@ def copy_calibration(nbytes):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="thermal64", choices=sorted(WORKLOAD_TEXT),
+                    help="thermal64 (the headline line) or one of the other workload families")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--tile", type=int, nargs=3, default=(4, 4, 4))
@@ -137,6 +232,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=40)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick tile shapes and sort interval with pic_autotune before timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run a plain copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -149,12 +246,22 @@ def main():
     import torch
     import pic_inputs as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    w = W.THERMAL64
+    wl = args.workload
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
 
-    log(f"FP32 form: {w['name']}, {args.warmup} warmup + {args.steps} timed steps")
-    r32 = time_form(w, False, args.steps, args.warmup, tuple(args.tile), args.sort_interval)
+    spec = workload(wl, tuple(args.tile))
+    sort_interval, tune = args.sort_interval, None
+    if args.autotune:
+        from paper_1308_5892_amd import pic as P
+        boxes, sort_interval, tune = P.autotune(spec["boxes"], spec["species"], spec["dt"], spec["loads"], steps=10,
+                                                sort_interval=args.sort_interval)
+        spec["boxes"] = boxes
+        shapes = sorted({tuple(b["tile"]) for b in boxes})
+        tune.update({"tiles": [list(t) for t in shapes], "sort_interval": sort_interval})
+        log(f"autotune: {tune}")
+    log(f"FP32 form: {WORKLOAD_TEXT[wl]}, {args.warmup} warmup + {args.steps} timed steps")
+    r32 = time_form(spec, False, args.steps, args.warmup, sort_interval)
     npart, cells = r32["npart"], r32["cells"]
     value = npart * args.steps / r32["seconds"]
     tm = r32["timing"]
@@ -163,7 +270,7 @@ def main():
     # each way), node-field read (6 x 4 B) and current flush (3 x 8 B) per cell
     push_bytes = 56.0 * npart + 48.0 * cells
     achieved = push_bytes / push_avg_s / 1e9
-    traffic = pmc_traffic()
+    traffic = pmc_traffic(wl)
     step_bytes = 56.0 * npart + 144.0 * cells
     log(f"FP32: {value / 1e9:.2f} G pushes/s, push kernel {push_avg_s * 1e3:.3f} ms "
         f"({achieved:.0f} GB/s), fields {tm['field_ms'] / max(1, tm['field_launches']):.3f} ms/step, "
@@ -172,7 +279,7 @@ def main():
     fp64 = None
     if not args.no_fp64:
         log(f"FP64 form: {args.fp64_steps} timed steps")
-        r64 = time_form(w, True, args.fp64_steps, 5, tuple(args.tile), args.sort_interval)
+        r64 = time_form(spec, True, args.fp64_steps, 5, sort_interval)
         v64 = r64["npart"] * args.fp64_steps / r64["seconds"]
         t64 = r64["timing"]
         p64 = t64["push_ms"] / max(1, t64["push_launches"]) / 1e3
@@ -183,9 +290,9 @@ def main():
         log(f"FP64: {v64 / 1e9:.2f} G pushes/s, speedup {value / v64:.2f}x")
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and wl == "thermal64":
         log("CPU oracle baseline (bounded sample)")
-        cpu = cpu_baseline(w)
+        cpu = cpu_baseline(W.THERMAL64)
         log(f"CPU: {cpu['value'] / 1e6:.2f} M pushes/s")
 
     d = r32["diag"]
@@ -193,9 +300,10 @@ def main():
         "metric": METRIC, "value": value, "unit": "pushes/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r32["seconds"] / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": w["name"] + ", 64 pairs/cell, theta=0.1, dt=0.5, n_x=10",
-                   "cells": cells, "particles": npart, "tile": list(args.tile),
-                   "sort_interval": args.sort_interval, "current": "int64 fixed point, 2^-31"},
+        "config": {"workload": WORKLOAD_TEXT[wl], "boxes": 256 if wl == "ensemble" else 1,
+                   "cells": cells, "particles": npart,
+                   "tile": list(args.tile) if tune is None else tune["tiles"],
+                   "sort_interval": sort_interval, "autotune": tune, "current": "int64 fixed point, 2^-31"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
@@ -204,8 +312,8 @@ def main():
                      "whole_step_frac": value * step_bytes / npart / 1e9 / HBM_PEAK_GBS},
         "cpu_baseline": cpu,
         "fp64_form": fp64,
-        "check": {"flags": d["flags"], "particles": int(d["count"].sum()),
-                  "gauss_max": d["gauss_max"], "overflow": int(d["n_overflow"].sum())},
+        "check": {"flags": d["flags"], "particles": d["count"], "gauss_max": d["gauss_max"],
+                  "overflow": d["n_overflow"]},
     }
     print(json.dumps(out), flush=True)
 

@@ -35,7 +35,8 @@
  * word that the next pic_diag or pic_sync reports as PIC_EFLAG.
  *
  * Limits: n[0], n[1] <= 2048, n[2] <= 1024; tile edges are powers of two
- * between 1 and 8; at most PIC_MAX_SPECIES species; fewer than 2^29 particle
+ * between 1 and 8, and the tile's push workgroup must fit in LDS (8x8x8 does
+ * not); at most PIC_MAX_SPECIES species; fewer than 2^29 particle
  * slots (capacity x headroom, plus 32 per tile and the overflow region) per
  * species per box; dt < 1/sqrt(3) (3-D Courant bound of the Yee scheme).
  */
@@ -251,6 +252,30 @@ int pic_free(pic_ctx *ctx);
 
 /* Message of the last error on ctx (static storage of the context). */
 const char *pic_last_error(const pic_ctx *ctx);
+
+/* Outcome of pic_autotune. */
+typedef struct pic_tune_result {
+    double  ms_per_step;          /* time per step of the chosen configuration */
+    double  ms_per_step_default;  /* time per step of cfg as given */
+    int32_t trials;               /* configurations timed */
+} pic_tune_result;
+
+/*
+ * Tile shape and sort interval by measurement (not part of the paper's
+ * method; the work split of this library).  Boxes are grouped by particle
+ * capacity per cell (below 32, below 128, above); for each group in turn the
+ * tile shapes 4x4x4, 8x4x4 and 8x8x4 are tried on the whole configuration,
+ * keeping the fastest, then the sort interval among 25, 50, 100 and cfg's.
+ * Each trial creates a context in dev_arena (borrowed, 256-byte aligned,
+ * `bytes` long; size it with pic_plan for cfg with its smallest tiles),
+ * applies the n_loads loads, runs steps/2 warm-up and `steps` timed steps on
+ * hip_stream, and frees the context; trials that do not fit the arena are
+ * skipped.  On PIC_OK, boxes_out (cfg->n_boxes entries, caller-owned) holds the
+ * boxes with the chosen tiles and *cfg_out the configuration, its boxes
+ * pointer set to boxes_out.  Synchronises; leaves no state behind.
+ */
+int pic_autotune(const pic_config *cfg, const pic_load_desc *loads, int n_loads, void *dev_arena, size_t bytes,
+                 void *hip_stream, int steps, pic_config *cfg_out, pic_box *boxes_out, pic_tune_result *res);
 
 #ifdef __cplusplus
 }

@@ -102,6 +102,10 @@ static void carve(Bump &A, const pic_config *cfg, std::vector<BoxHost> &bh, std:
     }
 }
 
+// LDS one workgroup may allocate on gfx950 (160 KiB per CU, minus the push
+// kernel's static counters)
+constexpr size_t kMaxLds = 160 * 1024 - 2048;
+
 static int validate(const pic_config *cfg, std::vector<BoxHost> &bh, std::string &err)
 {
     if (!cfg || cfg->n_boxes < 1 || !cfg->boxes) { err = "need at least one box"; return PIC_EINVAL; }
@@ -130,6 +134,9 @@ static int validate(const pic_config *cfg, std::vector<BoxHost> &bh, std::string
             if (t < 1 || t > 8 || (t & (t - 1))) { err = "tile edge must be 1, 2, 4 or 8"; return PIC_EINVAL; }
             H.tile[a] = t;
         }
+        const size_t lds = (cfg->flags & PIC_FP64_FORM) ? push_lds_bytes<double>(H.tile[0], H.tile[1], H.tile[2])
+                                                        : push_lds_bytes<float>(H.tile[0], H.tile[1], H.tile[2]);
+        if (lds > kMaxLds) { err = "tile needs more LDS than a workgroup may use"; return PIC_EINVAL; }
         if (!(H.cfg.n_x > 0) || !(H.cfg.rho0 > 0)) { err = "n_x and rho0 must be positive"; return PIC_EINVAL; }
         H.nc = (int64_t)H.cfg.n[0] * H.cfg.n[1] * H.cfg.n[2];
         H.ntiles = 1;
@@ -909,5 +916,102 @@ int pic_get_timing(pic_ctx *ctx, pic_timing *out, int reset)
             }
             v.clear();
         }
+    return PIC_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+
+// One trial: a context in the caller's arena, the loads, steps/2 warm-up and
+// `steps` timed steps on the stream; ms per step, or a negative value when the
+// configuration does not fit the arena or fails.
+static double tune_trial(const pic_config *cfg, const pic_load_desc *loads, int n_loads, void *arena, size_t bytes,
+                         void *stream, int steps)
+{
+    size_t need = 0;
+    if (pic_plan(cfg, &need) != PIC_OK || need > bytes) return -1.0;
+    pic_ctx *ctx = nullptr;
+    if (pic_init(cfg, arena, bytes, stream, &ctx) != PIC_OK) return -1.0;
+    double ms = -1.0;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+    for (int i = 0; ok && i < n_loads; ++i) ok = pic_load_maxwell_juttner(ctx, &loads[i]) == PIC_OK;
+    ok = ok && pic_step(ctx, std::max(1, steps / 2)) == PIC_OK && pic_sync(ctx) == PIC_OK;
+    ok = ok && hipEventRecord(a, ctx->stream) == hipSuccess && pic_step(ctx, steps) == PIC_OK &&
+         hipEventRecord(b, ctx->stream) == hipSuccess && pic_sync(ctx) == PIC_OK;
+    float t = 0.f;
+    if (ok && hipEventElapsedTime(&t, a, b) == hipSuccess) ms = t / steps;
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    pic_free(ctx);
+    return ms;
+}
+
+int pic_autotune(const pic_config *cfg, const pic_load_desc *loads, int n_loads, void *dev_arena, size_t bytes,
+                 void *hip_stream, int steps, pic_config *cfg_out, pic_box *boxes_out, pic_tune_result *res)
+{
+    if (!cfg || !cfg_out || !boxes_out || !res || steps < 1 || n_loads < 0 || (n_loads > 0 && !loads))
+        return PIC_EINVAL;
+    std::vector<BoxHost> bh;
+    std::string err;
+    int rc = validate(cfg, bh, err);
+    if (rc) return rc;
+    const int nb = cfg->n_boxes;
+    std::vector<pic_box> boxes(cfg->boxes, cfg->boxes + nb);
+    for (auto &b : boxes)
+        for (int a = 0; a < 3; ++a)
+            if (!b.tile[a]) b.tile[a] = 4;
+    pic_config c = *cfg;
+    c.boxes = boxes.data();
+    // density classes: superparticle capacity per cell below 32, below 128, above
+    std::vector<int> cls(nb);
+    for (int i = 0; i < nb; ++i) {
+        double np = 0;
+        for (int s = 0; s < cfg->n_species; ++s) np += (double)boxes[i].max_particles[s];
+        const double d = np / ((double)boxes[i].n[0] * boxes[i].n[1] * boxes[i].n[2]);
+        cls[i] = d < 32 ? 0 : (d < 128 ? 1 : 2);
+    }
+    res->trials = 0;
+    double best = tune_trial(&c, loads, n_loads, dev_arena, bytes, hip_stream, steps);
+    ++res->trials;
+    if (best < 0) return PIC_EDEVICE;
+    res->ms_per_step_default = best;
+    static const int cand[][3] = {{4, 4, 4}, {8, 4, 4}, {8, 8, 4}};
+    for (int k = 0; k < 3; ++k) {
+        std::vector<int> members;
+        for (int i = 0; i < nb; ++i)
+            if (cls[i] == k) members.push_back(i);
+        if (members.empty()) continue;
+        int keep[3] = {boxes[members[0]].tile[0], boxes[members[0]].tile[1], boxes[members[0]].tile[2]};
+        for (const auto &t : cand) {
+            if (t[0] == keep[0] && t[1] == keep[1] && t[2] == keep[2]) continue;
+            for (int i : members)
+                for (int a = 0; a < 3; ++a) boxes[i].tile[a] = t[a];
+            const double ms = tune_trial(&c, loads, n_loads, dev_arena, bytes, hip_stream, steps);
+            ++res->trials;
+            if (ms > 0 && ms < best) {
+                best = ms;
+                for (int a = 0; a < 3; ++a) keep[a] = t[a];
+            }
+        }
+        for (int i : members)
+            for (int a = 0; a < 3; ++a) boxes[i].tile[a] = keep[a];
+    }
+    const int si_keep = c.sort_interval;
+    int si_best = si_keep;
+    for (int si : {25, 50, 100}) {
+        if (si == si_keep) continue;
+        c.sort_interval = si;
+        const double ms = tune_trial(&c, loads, n_loads, dev_arena, bytes, hip_stream, steps);
+        ++res->trials;
+        if (ms > 0 && ms < best) {
+            best = ms;
+            si_best = si;
+        }
+    }
+    c.sort_interval = si_best;
+    res->ms_per_step = best;
+    std::copy(boxes.begin(), boxes.end(), boxes_out);
+    *cfg_out = c;
+    cfg_out->boxes = boxes_out;
     return PIC_OK;
 }

@@ -26,7 +26,7 @@ ERROR_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ECOURANT", -3: "PIC_ENOME
 EXPORTED = ["pic_plan", "pic_init", "pic_load_maxwell_juttner", "pic_set_harris_field", "pic_step",
             "pic_diag", "pic_get_particles", "pic_set_particles", "pic_get_fields", "pic_set_fields",
             "pic_sync", "pic_steps_done", "pic_free", "pic_last_error", "pic_set_timing",
-            "pic_get_timing"]
+            "pic_get_timing", "pic_autotune"]
 
 
 class pic_species(C.Structure):
@@ -75,6 +75,10 @@ class pic_timing(C.Structure):
                 ("field_ms", C.c_double), ("sort_launches", C.c_int64), ("sort_ms", C.c_double)]
 
 
+class pic_tune_result(C.Structure):
+    _fields_ = [("ms_per_step", C.c_double), ("ms_per_step_default", C.c_double), ("trials", C.c_int32)]
+
+
 class PicError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
@@ -112,6 +116,9 @@ def lib():
         L.pic_last_error.restype = C.c_char_p
         L.pic_set_timing.argtypes = [C.c_void_p, C.c_int]
         L.pic_get_timing.argtypes = [C.c_void_p, C.POINTER(pic_timing), C.c_int]
+        L.pic_autotune.argtypes = [C.POINTER(pic_config), C.POINTER(pic_load_desc), C.c_int, C.c_void_p, C.c_size_t,
+                                   C.c_void_p, C.c_int, C.POINTER(pic_config), C.POINTER(pic_box),
+                                   C.POINTER(pic_tune_result)]
         for name in EXPORTED:
             if name not in ("pic_steps_done", "pic_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -243,6 +250,19 @@ def pic_get_timing(ctx, reset=True):
             "field_ms": t.field_ms, "sort_launches": t.sort_launches, "sort_ms": t.sort_ms}
 
 
+def pic_autotune(cfg, loads, arena_ptr, nbytes, stream_ptr, steps):
+    """Returns (tuned pic_config, its pic_box array, pic_tune_result)."""
+    arr = (pic_load_desc * max(1, len(loads)))(*loads)
+    boxes = (pic_box * cfg.n_boxes)()
+    out = pic_config()
+    res = pic_tune_result()
+    _check(lib().pic_autotune(C.byref(cfg), C.cast(arr, C.POINTER(pic_load_desc)), len(loads), C.c_void_p(arena_ptr),
+                              nbytes, C.c_void_p(stream_ptr), int(steps), C.byref(out),
+                              C.cast(boxes, C.POINTER(pic_box)), C.byref(res)))
+    out._boxes_keepalive = boxes
+    return out, boxes, res
+
+
 def pic_free(ctx):
     _check(lib().pic_free(ctx))
 
@@ -262,6 +282,26 @@ def load_desc(box, species_a, species_b, mj_a, mj_b, ppc, seed, stream=0, profil
 
 
 # --------------------------------------------------- torch-backed simulation
+
+def autotune(boxes, species, dt, loads, steps=10, **kw):
+    """pic_autotune with a torch arena on the current device and torch's current
+    stream.  loads: pic_load_desc list.  Returns (boxes with the chosen tiles,
+    sort interval, {"ms_per_step", "ms_per_step_default", "trials"})."""
+    import torch
+    cfg = make_config(boxes, species, dt, **kw)
+    nbytes = pic_plan(cfg)
+    arena = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    base = (arena.data_ptr() + 255) & ~255
+    out, arr, res = pic_autotune(cfg, loads, base, nbytes, torch.cuda.current_stream().cuda_stream, steps)
+    del arena
+    tuned = []
+    for i, b in enumerate(boxes):
+        t = dict(b)
+        t["tile"] = tuple(arr[i].tile[:])
+        tuned.append(t)
+    return tuned, out.sort_interval, {"ms_per_step": res.ms_per_step, "ms_per_step_default": res.ms_per_step_default,
+                                      "trials": res.trials}
+
 
 class Simulation:
     """A pic context whose arena is a torch uint8 tensor on the current device and

@@ -43,7 +43,7 @@ def test_struct_layout_matches_header(P, tmp_path):
         "pic_species": P.pic_species, "pic_box": P.pic_box, "pic_config": P.pic_config,
         "pic_mj": P.pic_mj, "pic_load_desc": P.pic_load_desc,
         "pic_harris_field": P.pic_harris_field, "pic_diag_out": P.pic_diag_out,
-        "pic_timing": P.pic_timing,
+        "pic_timing": P.pic_timing, "pic_tune_result": P.pic_tune_result,
     }
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "pic.h"', "int main(void){"]
     for name, cls in structs.items():
@@ -84,6 +84,7 @@ def test_plan_sizes(P):
     {"box": {"n": (4096, 4, 4)}},
     {"box": {"tile": (3, 4, 4)}},
     {"box": {"tile": (16, 4, 4)}},
+    {"box": {"tile": (8, 8, 8)}},            # the push workgroup would not fit in LDS
     {"box": {"n_x": 0.0}},
     {"dt": -0.1},
     {"headroom": 1.01},

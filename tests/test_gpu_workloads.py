@@ -314,3 +314,30 @@ def test_full_size_harris_512x256x4():
     _full_size_check(s, dims, w["dt"], w["n_x"], w["rho0"], species, parts, e0, b0, 3,
                      2.0 / (w["n_x"] ** 2 * w["rho0"]) * w["ppc"])
     s.close()
+
+
+def test_autotune_picks_a_working_configuration():
+    from paper_1308_5892_amd import pic as P
+    spec = W.ENSEMBLE_SMALL
+    blist = W.ensemble_boxes(spec)
+    boxes, loads = [], []
+    for i, bx in enumerate(blist):
+        npairs = bx["ppc"] * int(np.prod(bx["dims"]))
+        boxes.append({"n": bx["dims"], "n_x": spec["n_x"], "rho0": 2.0 * bx["ppc"],
+                      "max_particles": [npairs, npairs]})
+        loads.append(P.load_desc(i, 0, 1, (bx["theta"], 0.0, 1), (bx["theta"], 0.0, 1), bx["ppc"], seed=bx["seed"]))
+    tuned, si, res = P.autotune(boxes, G.PAIR, spec["dt"], loads, steps=2, sort_interval=50)
+    assert res["trials"] >= 4 and 0 < res["ms_per_step"] <= res["ms_per_step_default"]
+    assert si in (25, 50, 100)
+    for b in tuned:
+        assert tuple(b["tile"]) in ((4, 4, 4), (8, 4, 4), (8, 8, 4))
+    # the tuned configuration runs and keeps every particle
+    sim = P.Simulation(tuned, G.PAIR, spec["dt"], sort_interval=si)
+    for d in loads:
+        P.pic_load_maxwell_juttner(sim.ctx, d)
+    sim.step(2 * si + 3)
+    for i, bx in enumerate(blist):
+        d = sim.diag(i)
+        assert d["flags"] == 0
+        assert d["count"].tolist() == [bx["ppc"] * int(np.prod(bx["dims"]))] * 2
+    sim.close()

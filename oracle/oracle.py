@@ -55,11 +55,12 @@ def lib():
         L.orc_deposit_move.restype = C.c_int
         L.orc_deposit_charge.argtypes = [G, C.c_double, _dp, _dp]
         L.orc_step.argtypes = [G, C.c_double, C.c_double, C.c_int, _dp, _dp, C.c_int64,
-                               _ip, _dp, _dp, _dp, _dp, C.c_int]
+                               _ip, _dp, _dp, _dp, _dp, C.c_int, C.c_int]
+        L.orc_filter27.argtypes = [G, C.c_int, _dp]
         L.orc_backward_half.argtypes = [G, C.c_double, _dp, C.c_int64, _ip, _dp, _dp, _dp, _dp]
         L.orc_diag.argtypes = [G, C.c_double, C.c_double, C.c_int, _dp, _dp, _dp, C.c_int64,
                                _ip, _dp, _dp, _dp, _dp, _dp, C.c_int, C.c_double, C.c_double,
-                               C.c_void_p]
+                               C.c_void_p, C.c_int]
         L.orc_philox4x64.argtypes = [_up, _up, _up]
         L.orc_mj_range.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_mj_table.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, _dp]
@@ -137,6 +138,14 @@ def deposit_move(dims, sgn, x0, x1, J=None):
     return J, npieces
 
 
+def filter27(dims, f):
+    """The 27-point current smoothing of App. A.3.4 on each component grid."""
+    f = _f(f).copy()
+    n = int(np.prod(dims))
+    lib().orc_filter27(_g(dims), len(f) // n, f)
+    return f
+
+
 def deposit_charge(dims, sgn, x, rho=None):
     """CIC node weights of a particle at x (App. A.3.3)."""
     rho = np.zeros(int(np.prod(dims))) if rho is None else rho
@@ -164,6 +173,7 @@ class State:
         self.x = np.zeros((0, 3))
         self.u = np.zeros((0, 3))
         self.species = np.zeros(0, dtype=np.int32)
+        self.filter = False                      # smooth the current (App. A.3.4)
 
     def add_particles(self, s, x, u):
         self.x = np.concatenate([self.x, _f(x).reshape(-1, 3)])
@@ -176,7 +186,7 @@ class State:
         u = np.ascontiguousarray(self.u).reshape(-1)
         lib().orc_step(_g(self.dims), self.dt, self.alpha0, len(self.kq), self.kq, self.sgn,
                        len(self.species), np.ascontiguousarray(self.species), x, u,
-                       self.e, self.b, int(nsteps))
+                       self.e, self.b, int(nsteps), int(self.filter))
         self.x = x.reshape(-1, 3)
         self.u = u.reshape(-1, 3)
 
@@ -202,7 +212,7 @@ class State:
         lib().orc_diag(_g(self.dims), self.dt, self.alpha0, nsp, self.kq, self.sgn, self.m,
                        len(self.species), np.ascontiguousarray(self.species), x, u,
                        self.e, self.b, out, int(nbins), float(lo), float(hi),
-                       hist.ctypes.data if nbins > 0 else None)
+                       hist.ctypes.data if nbins > 0 else None, int(self.filter))
         d = {
             "W_E": out[0:3].copy(), "W_B": out[3:6].copy(),
             "gauss_max": out[6], "gauss_rms": out[7],

@@ -352,16 +352,48 @@ static double wrapd(double x, int n)
 }
 
 /*
+ * Smoothing of the current (App. A.3.4, last paragraph): each value of a grid
+ * becomes the weighted sum of the 27 values around it - weight 1 for itself,
+ * 1/2 for its 6 face neighbours, 1/4 for its 12 edge neighbours, 1/8 for its 8
+ * corner neighbours - with the weights normalised to sum to one (their sum is
+ * 8).  Periodic; applied to each of the ncomp component grids of f in place.
+ */
+void orc_filter27(const int g[3], int ncomp, double *f)
+{
+    int64_t n = ncells(g);
+    double *t = (double *)malloc(sizeof(double) * n);
+    for (int c = 0; c < ncomp; ++c) {
+        double *fc = f + (int64_t)c * n;
+        memcpy(t, fc, sizeof(double) * n);
+        for (int k = 0; k < g[2]; ++k)
+            for (int j = 0; j < g[1]; ++j)
+                for (int i = 0; i < g[0]; ++i) {
+                    double sum = 0.0;
+                    for (int dk = -1; dk <= 1; ++dk)
+                        for (int dj = -1; dj <= 1; ++dj)
+                            for (int di = -1; di <= 1; ++di) {
+                                int m = abs(di) + abs(dj) + abs(dk);   /* 0 self, 1 face, 2 edge, 3 corner */
+                                double w = m == 0 ? 1.0 : (m == 1 ? 0.5 : (m == 2 ? 0.25 : 0.125));
+                                sum += w * t[cell_index(g, i + di, j + dj, k + dk)];
+                            }
+                    fc[cell_index(g, i, j, k)] = sum / 8.0;
+                }
+    }
+    free(t);
+}
+
+/*
  * nsteps leap-frog cycles (App. A.3.1).  On entry x and e are at time t, u and
  * b at t - dt/2; on return they have advanced by nsteps*dt.
  * Particles: x[3p..3p+2] in [0, N), u likewise, species[p] in [0, nsp).
  * kq[s] = (q_s/e)(m_e/m_s), sgn[s] = sgn(q_s), alpha0 = 2/(n_x^2 rho0).
- * The filter (item 10) is off and every boundary is periodic.
+ * filter != 0 smooths the current (orc_filter27) before it enters e; every
+ * boundary is periodic.
  */
 void orc_step(const int g[3], double dt, double alpha0, int nsp,
               const double *kq, const double *sgn, int64_t np,
               const int32_t *species, double *x, double *u,
-              double *e, double *b, int nsteps)
+              double *e, double *b, int nsteps, int filter)
 {
     int64_t n = ncells(g);
     double *J = (double *)malloc(sizeof(double) * 3 * n);
@@ -392,6 +424,8 @@ void orc_step(const int g[3], double dt, double alpha0, int nsp,
         memset(J, 0, sizeof(double) * 3 * n);
         for (int64_t p = 0; p < np; ++p)
             orc_deposit_move(g, sgn[species[p]], &xold[3 * p], &x[3 * p], J);
+        /* 10. optional smoothing of the current (App. A.3.4) */
+        if (filter) orc_filter27(g, 3, J);
         /* 12. e += alpha0 * sum_s sgn_s dV  (App. A.2, eq. max2bis) */
         for (int64_t q = 0; q < 3 * n; ++q)
             e[q] += alpha0 * J[q];
@@ -428,7 +462,8 @@ void orc_backward_half(const int g[3], double dt, const double *kq, int64_t np,
  *   [0..2]  W_E,c = (1/alpha0) sum 1/2 e_c^2        (energy unit of Fig. fluctuations, Sect. 5.3)
  *   [3..5]  W_B,c = (1/alpha0) sum 1/2 (b^t)_c^2, b^t = b - (dt/2) curl e
  *   [6]     max |div e - rho|,  [7] rms of the same,
- *           rho = alpha0 sum_s sgn_s sum_p W(x_p)
+ *           rho = alpha0 sum_s sgn_s sum_p W(x_p), smoothed like the
+ *           current when filter != 0
  *   then per species s (8 + 6 s): K_s = sum (m_s/m_e)(gamma^t - 1),
  *           P_s[3] = sum u^-, count, sum (gamma^t - 1)
  * READING (the paper does not say at which time it evaluates the energies):
@@ -441,7 +476,7 @@ void orc_diag(const int g[3], double dt, double alpha0, int nsp, const double *k
               const double *sgn, const double *m_over_me, int64_t np,
               const int32_t *species, const double *x, const double *u,
               const double *e, const double *b, double *out,
-              int nbins, double lo, double hi, int64_t *hist)
+              int nbins, double lo, double hi, int64_t *hist, int filter)
 {
     int64_t n = ncells(g);
     double *bt = (double *)malloc(sizeof(double) * 3 * n);
@@ -484,6 +519,8 @@ void orc_diag(const int g[3], double dt, double alpha0, int nsp, const double *k
         }
         orc_deposit_charge(g, sgn[s] * alpha0, &x[3 * p], rho);
     }
+    /* with a smoothed current, the conserved charge is the smoothed one */
+    if (filter) orc_filter27(g, 1, rho);
     double rmax = 0.0, rsum = 0.0;
     for (int k = 0; k < g[2]; ++k)
         for (int j = 0; j < g[1]; ++j)

@@ -142,7 +142,8 @@ def workload(name, tile):
 def make_sim(wl, fp64, sort_interval):
     """Build and load a workload; returns (sim, particles, cells)."""
     from paper_1308_5892_amd import pic as P
-    sim = P.Simulation(wl["boxes"], wl["species"], wl["dt"], fp64=fp64, sort_interval=sort_interval)
+    sim = P.Simulation(wl["boxes"], wl["species"], wl["dt"], fp64=fp64, sort_interval=sort_interval,
+                       filter_current=wl.get("filter", False))
     for h in wl["harris"]:
         sim.harris_field(*h)
     for d in wl["loads"]:
@@ -232,6 +233,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=40)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--filter-current", action="store_true",
+                    help="smooth the current with the 27-point filter before it enters e")
     ap.add_argument("--autotune", action="store_true",
                     help="pick tile shapes and sort interval with pic_autotune before timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -251,6 +254,7 @@ def main():
         copy_calibration(args.copy_calibration)
 
     spec = workload(wl, tuple(args.tile))
+    spec["filter"] = args.filter_current
     sort_interval, tune = args.sort_interval, None
     if args.autotune:
         from paper_1308_5892_amd import pic as P
@@ -303,7 +307,7 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[wl], "boxes": 256 if wl == "ensemble" else 1,
                    "cells": cells, "particles": npart,
                    "tile": list(args.tile) if tune is None else tune["tiles"],
-                   "sort_interval": sort_interval, "autotune": tune, "current": "int64 fixed point, 2^-31"},
+                   "sort_interval": sort_interval, "autotune": tune, "filter_current": args.filter_current, "current": "int64 fixed point, 2^-31"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,

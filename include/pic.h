@@ -6,7 +6,8 @@
  * staggered Yee grid (App. A.3.3), relativistic Boris push and move (App. A.3.3,
  * eq. mover), charge-conserving volume-weighting current deposit (App. A.1 and
  * A.3.4, eq. current_dep) and the Yee update of b and e (App. A.3.2), with
- * periodic boundaries (App. A.4).  The current filter of item 10 is not applied.
+ * periodic boundaries (App. A.4).  The current filter of item 10 (App. A.3.4) is
+ * optional (PIC_FILTER_CURRENT).
  *
  * Units are the paper's normalised ones (App. A.2): lengths in cells (dx = 1),
  * times in X0/c, e and b = cB in m_e c^2/(e X0), u = gamma v / c.  Species s has
@@ -63,6 +64,11 @@ extern "C" {
 /* pic_config.flags */
 #define PIC_FP64_FORM 1u   /* FP64 storage and arithmetic, FP64 atomics (reference form) */
 #define PIC_TRACK_IDS 2u   /* carry a 32-bit particle id (parity and checkpoints) */
+#define PIC_FILTER_CURRENT 4u  /* smooth the current before it enters e (App. A.3.4, last
+                                  paragraph: weight 1 for the value itself, 1/2 for the 6 face,
+                                  1/4 for the 12 edge and 1/8 for the 8 corner neighbours,
+                                  normalised to one); the Gauss residual of pic_diag then uses
+                                  the charge smoothed the same way */
 
 /* pic_load_desc.profile */
 #define PIC_PROFILE_UNIFORM 0

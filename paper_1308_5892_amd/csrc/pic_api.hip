@@ -117,6 +117,10 @@ static int validate(const pic_config *cfg, std::vector<BoxHost> &bh, std::string
         }
     }
     if (!(cfg->dt > 0)) { err = "dt must be positive"; return PIC_EINVAL; }
+    if (cfg->flags & ~(uint32_t)(PIC_FP64_FORM | PIC_TRACK_IDS | PIC_FILTER_CURRENT)) {
+        err = "unknown flag";
+        return PIC_EINVAL;
+    }
     if (cfg->hist_bins < 0 || (cfg->hist_bins > 0 && !(cfg->hist_hi > cfg->hist_lo))) {
         err = "bad histogram range";
         return PIC_EINVAL;
@@ -289,6 +293,7 @@ static StepConst<R> step_const(pic_ctx *ctx)
     C.hist_bins = ctx->cfg.hist_bins;
     C.hist_lo = ctx->cfg.hist_lo;
     C.hist_hi = ctx->cfg.hist_hi;
+    C.filter = (ctx->cfg.flags & PIC_FILTER_CURRENT) != 0;
     return C;
 }
 
@@ -486,8 +491,8 @@ static int step_t(pic_ctx *ctx, int n)
         HIPCHK(launch_push<R>(boxes, ctx->L.items_push, ctx->L.n_items, ctx->lds_bytes, C, ctx->stream));
         mark(ctx, 0, false);
         mark(ctx, 1, true);
-        HIPCHK(launch_fields<R>(boxes, ctx->L.cblocks, ctx->L.n_cblocks, (R)ctx->cfg.dt, ctx->cfg.n_species, ctx->cur,
-                                ctx->stream));
+        HIPCHK(launch_fields<R>(boxes, ctx->L.cblocks, ctx->L.n_cblocks, (R)ctx->cfg.dt, ctx->cfg.n_species, C.filter,
+                                ctx->cur, ctx->stream));
         mark(ctx, 1, false);
         ctx->cur ^= 1;
         ctx->step += 1;

@@ -108,6 +108,7 @@ struct StepConst {
     int32_t cur;                   // copy read this step
     int32_t hist_bins;
     double hist_lo, hist_hi;
+    int32_t filter;                // smooth the current (and the Gauss charge)
 };
 
 // diagnostic accumulator layout per box
@@ -173,7 +174,7 @@ template <typename R>
 hipError_t launch_push(const BoxDev<R> *boxes, const Item *items, int nitems, size_t lds, const StepConst<R> &C,
                        hipStream_t st);
 template <typename R>
-hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R dt, int nsp,
+hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R dt, int nsp, int filter,
                          int clear_copy, hipStream_t st);
 template <typename R>
 hipError_t launch_advance_b(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R h, hipStream_t st);

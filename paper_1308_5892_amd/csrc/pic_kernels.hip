@@ -1113,6 +1113,75 @@ __global__ void __launch_bounds__(kBlock) advance_e_kernel(const BoxDev<R> *__re
     J[2 * B.nc + p] = JT(0);
 }
 
+// Sum over the 27 values around cell (i,j,k) of one periodic grid with the
+// smoothing weights of App. A.3.4 scaled to integers: 8 for the cell itself,
+// 4 per face neighbour, 2 per edge neighbour, 1 per corner neighbour (the
+// paper's 1, 1/2, 1/4, 1/8 times 8; they add up to 64).
+template <typename T>
+__device__ inline T smooth27(const PIC_GLOBAL T *f, const int n[3], int i, int j, int k)
+{
+    T acc = T(0);
+#pragma unroll
+    for (int dk = -1; dk <= 1; ++dk) {
+        const int64_t kk = wrap1(k + dk, n[2]);
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj) {
+            const int64_t row = (int64_t)n[0] * (wrap1(j + dj, n[1]) + (int64_t)n[1] * kk);
+#pragma unroll
+            for (int di = -1; di <= 1; ++di) {
+                const int w = 8 >> ((di != 0) + (dj != 0) + (dk != 0));
+                acc += T(w) * f[row + wrap1(i + di, n[0])];
+            }
+        }
+    }
+    return acc;
+}
+
+// e <- e + dt curl b + alpha0 S J with S the 27-point smoothing of App. A.3.4
+// (integer weights in the FP32 form, so the smoothed current stays exact and
+// order-independent until its one conversion); J is cleared afterwards by
+// clear_current_kernel, since every cell reads its neighbours' J here.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) advance_e_smoothed_kernel(const BoxDev<R> *__restrict__ boxes,
+                                                                    const CellBlock *__restrict__ blocks, R dt)
+{
+    using JT = typename JType<R>::T;
+    const CellBlock cb = blocks[blockIdx.x];
+    const BoxDev<R> &B = boxes[cb.box];
+    const int64_t p = (int64_t)cb.first + threadIdx.x;
+    if (p >= B.nc) return;
+    const int n0 = B.n[0], n1 = B.n[1], n2 = B.n[2];
+    const int i = (int)(p % n0), j = (int)((p / n0) % n1), k = (int)(p / ((int64_t)n0 * n1));
+    const int64_t sx = (i > 0) ? 1 : 1 - n0;
+    const int64_t sy = (j > 0) ? n0 : (int64_t)n0 * (1 - n1);
+    const int64_t sz = (k > 0) ? (int64_t)n0 * n1 : (int64_t)n0 * n1 * (1 - n2);
+    const R *bx = B.b, *by = B.b + B.nc, *bz = B.b + 2 * B.nc;
+    const R cx = (bz[p] - bz[p - sy]) - (by[p] - by[p - sz]);
+    const R cy = (bx[p] - bx[p - sz]) - (bz[p] - bz[p - sx]);
+    const R cz = (by[p] - by[p - sx]) - (bx[p] - bx[p - sy]);
+    const double a = B.alpha0 / (double)qscale_bits<R>() / 64.0;
+    const R cur[3] = {cx, cy, cz};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const JT s = smooth27<JT>(B.J + c * B.nc, B.n, i, j, k);
+        B.e[c * B.nc + p] += dt * cur[c] + (R)(a * (double)s);
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) clear_current_kernel(const BoxDev<R> *__restrict__ boxes,
+                                                               const CellBlock *__restrict__ blocks)
+{
+    using JT = typename JType<R>::T;
+    const CellBlock cb = blocks[blockIdx.x];
+    const BoxDev<R> &B = boxes[cb.box];
+    const int64_t p = (int64_t)cb.first + threadIdx.x;
+    if (p >= B.nc) return;
+    B.J[p] = JT(0);
+    B.J[B.nc + p] = JT(0);
+    B.J[2 * B.nc + p] = JT(0);
+}
+
 // ------------------------------------------------------ counting-sort repack
 
 // The particles of a work item in copy c: a tile's A and B ranges (one block
@@ -1378,7 +1447,7 @@ __device__ inline void atomic_max_pos(double *p, double v)
 // Field energies (e^t, b^t) and the Gauss-law residual div e - rho at the nodes.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) diag_fields_kernel(const BoxDev<R> *__restrict__ boxes, int box,
-                                                             R dt)
+                                                             R dt, int filter)
 {
     const BoxDev<R> &B = boxes[box];
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1396,7 +1465,9 @@ __global__ void __launch_bounds__(kBlock) diag_fields_kernel(const BoxDev<R> *__
         const double div = (double)fld(B.e, B, 0, i, j, k) - (double)fld(B.e, B, 0, i - 1, j, k) +
                            (double)fld(B.e, B, 1, i, j, k) - (double)fld(B.e, B, 1, i, j - 1, k) +
                            (double)fld(B.e, B, 2, i, j, k) - (double)fld(B.e, B, 2, i, j, k - 1);
-        const double r = div - B.rho[p];
+        // with a smoothed current the conserved charge is the smoothed one
+        const double rho = filter ? smooth27<double>(B.rho, B.n, i, j, k) / 64.0 : B.rho[p];
+        const double r = div - rho;
         v[6] = r * r;
         gmax = fabs(r);
     }
@@ -1429,11 +1500,16 @@ hipError_t launch_push(const BoxDev<R> *boxes, const Item *items, int nitems, si
 }
 
 template <typename R>
-hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R dt, int nsp,
+hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R dt, int nsp, int filter,
                          int clear_copy, hipStream_t st)
 {
     hipLaunchKernelGGL(advance_b_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt, nsp, clear_copy);
-    hipLaunchKernelGGL(advance_e_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt);
+    if (filter) {
+        hipLaunchKernelGGL(advance_e_smoothed_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt);
+        hipLaunchKernelGGL(clear_current_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks);
+    } else {
+        hipLaunchKernelGGL(advance_e_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt);
+    }
     return hipGetLastError();
 }
 
@@ -1465,7 +1541,7 @@ hipError_t launch_diag(const BoxDev<R> *boxes, int box, int64_t nc, const Item *
 {
     if (nitems) hipLaunchKernelGGL(diag_particles_kernel<R>, dim3(nitems), dim3(kBlock), 0, st, boxes, items, C);
     const int nb = (int)((nc + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(diag_fields_kernel<R>, dim3(nb), dim3(kBlock), 0, st, boxes, box, C.dt);
+    hipLaunchKernelGGL(diag_fields_kernel<R>, dim3(nb), dim3(kBlock), 0, st, boxes, box, C.dt, C.filter);
     return hipGetLastError();
 }
 
@@ -1473,7 +1549,8 @@ hipError_t launch_diag(const BoxDev<R> *boxes, int box, int64_t nc, const Item *
     template size_t push_lds_bytes<R>(int, int, int);                                                         \
     template hipError_t launch_push<R>(const BoxDev<R> *, const Item *, int, size_t, const StepConst<R> &,   \
                                        hipStream_t);                                                          \
-    template hipError_t launch_fields<R>(const BoxDev<R> *, const CellBlock *, int, R, int, int, hipStream_t); \
+    template hipError_t launch_fields<R>(const BoxDev<R> *, const CellBlock *, int, R, int, int, int,          \
+                                         hipStream_t);                                                        \
     template hipError_t launch_advance_b<R>(const BoxDev<R> *, const CellBlock *, int, R, hipStream_t);       \
     template hipError_t launch_repack<R>(const BoxDev<R> *, int, const Item *, int, const StageItem *, int,    \
                                          const StepConst<R> &, hipStream_t);                                  \

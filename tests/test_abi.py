@@ -96,6 +96,14 @@ def test_plan_rejects_bad_config(P, bad):
     assert ei.value.code == P.PIC_EINVAL
 
 
+def test_plan_rejects_unknown_flag(P):
+    cfg = _cfg(P)
+    cfg.flags |= 64
+    with pytest.raises(P.PicError) as ei:
+        P.pic_plan(cfg)
+    assert ei.value.code == P.PIC_EINVAL
+
+
 def test_plan_rejects_bad_species(P):
     cfg = P.make_config([{"n": (8, 8, 8), "n_x": 10.0, "rho0": 2.0, "max_particles": [10]}],
                         [(-0.5, 1.0)], 0.5)

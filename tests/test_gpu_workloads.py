@@ -71,6 +71,40 @@ def test_energy_curve_fp64_form_follows_oracle_100_steps():
     s.close()
 
 
+@pytest.mark.parametrize("fp64,tol", [(False, 1e-5), (True, 1e-11)])
+def test_smoothed_current_ten_steps(fp64, tol):
+    # the 27-point current smoothing of App. A.3.4 on the thermal 16^3 plasma:
+    # per-particle momentum after 10 steps, fields, and Gauss's law with the
+    # smoothed charge
+    w = W.THERMAL16
+    dims, ppc = w["dims"], w["ppc"]
+    npairs = ppc * int(np.prod(dims))
+    mj = {"theta": w["theta"], "gb": 0.0, "axis": 1}
+    parts = G.oracle_loaded(dims, w["dt"], w["n_x"], 2 * ppc, G.PAIR,
+                            [dict(seed=w["seed"], stream=0, npairs=npairs, A=mj, B=mj)])
+    s = G.sim(dims, w["n_x"], 2 * ppc, [npairs, npairs], dt=w["dt"], fp64=fp64, filter_current=True)
+    st = G.oracle_state(dims, w["n_x"], 2 * ppc, w["dt"])
+    st.filter = True
+    G.start(s, st, parts, fp64=fp64)
+    worst = _ten_steps(s, st, dims, tol)
+    assert worst < tol, worst
+    e, _, _ = s.fields(0)
+    assert np.abs(e - st.e).max() < (1e-12 if fp64 else 1e-4) * np.abs(st.e).max()
+    d, r = s.diag(0), st.diag()
+    assert d["flags"] == 0
+    assert r["gauss_max"] < 1e-13
+    assert d["gauss_max"] < (1e-13 if fp64 else 1e-4 * 2.0 / (w["n_x"] ** 2 * 2 * ppc) * ppc), d["gauss_max"]
+    # the smoothed run differs from the unsmoothed one
+    s2 = G.sim(dims, w["n_x"], 2 * ppc, [npairs, npairs], dt=w["dt"], fp64=fp64)
+    st2 = G.oracle_state(dims, w["n_x"], 2 * ppc, w["dt"])
+    G.start(s2, st2, parts, fp64=fp64)
+    s2.step(10)
+    e2, _, _ = s2.fields(0)
+    assert np.abs(e2 - e).max() > 0.1 * np.abs(e).max()
+    s.close()
+    s2.close()
+
+
 def _ten_steps(s, st, dims, tol, nsp=2, box=0):
     s.step(10)
     st.step(10)

@@ -75,7 +75,7 @@ extern "C" {
 #define PIC_PROFILE_HARRIS  1
 
 /* device error flag bits, reported through pic_diag_out.flags */
-#define PIC_FLAG_NONFINITE 1u  /* a momentum became NaN or infinite */
+#define PIC_FLAG_NONFINITE 1u  /* a momentum became NaN, infinite or larger than 1e15 */
 #define PIC_FLAG_LOST      2u  /* a tile segment and the overflow region were full */
 
 typedef struct pic_species {

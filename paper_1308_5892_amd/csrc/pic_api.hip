@@ -218,6 +218,7 @@ struct pic_ctx {
     int cur = 0;
     int64_t step = 0;
     size_t lds_bytes = 0;
+    bool fixed444 = false;             // every tile 4x4x4: the fixed-shape push kernel
     bool pending = false;
     uint32_t flags_seen = 0;
     std::string err;
@@ -372,8 +373,13 @@ static int init_t(pic_ctx *ctx)
     HIPCHK(hipMemcpyAsync(ctx->L.cblocks, cbs.data(), cbs.size() * sizeof(CellBlock), hipMemcpyHostToDevice,
                           ctx->stream));
     size_t lds = 0;
-    for (auto &H : ctx->bh) lds = std::max(lds, push_lds_bytes<R>(H.tile[0], H.tile[1], H.tile[2]));
+    bool all444 = true;
+    for (auto &H : ctx->bh) {
+        lds = std::max(lds, push_lds_bytes<R>(H.tile[0], H.tile[1], H.tile[2]));
+        all444 = all444 && H.tile[0] == 4 && H.tile[1] == 4 && H.tile[2] == 4;
+    }
     ctx->lds_bytes = lds;
+    ctx->fixed444 = all444;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     // initial segment layout: an empty repack
     return merge_t<R>(ctx, true);
@@ -488,7 +494,8 @@ static int step_t(pic_ctx *ctx, int n)
     for (int i = 0; i < n; ++i) {
         StepConst<R> C = step_const<R>(ctx);
         mark(ctx, 0, true);
-        HIPCHK(launch_push<R>(boxes, ctx->L.items_push, ctx->L.n_items, ctx->lds_bytes, C, ctx->stream));
+        HIPCHK(launch_push<R>(boxes, ctx->L.items_push, ctx->L.n_items, ctx->lds_bytes, C, ctx->fixed444 ? 1 : 0,
+                              ctx->stream));
         mark(ctx, 0, false);
         mark(ctx, 1, true);
         HIPCHK(launch_fields<R>(boxes, ctx->L.cblocks, ctx->L.n_cblocks, (R)ctx->cfg.dt, ctx->cfg.n_species, C.filter,

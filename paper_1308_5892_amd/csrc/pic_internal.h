@@ -172,7 +172,7 @@ struct LoadArgs {
 template <typename R> size_t push_lds_bytes(int t0, int t1, int t2);
 template <typename R>
 hipError_t launch_push(const BoxDev<R> *boxes, const Item *items, int nitems, size_t lds, const StepConst<R> &C,
-                       hipStream_t st);
+                       int fixed444, hipStream_t st);
 template <typename R>
 hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R dt, int nsp, int filter,
                          int clear_copy, hipStream_t st);

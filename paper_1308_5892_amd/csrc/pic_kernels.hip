@@ -345,20 +345,27 @@ struct TileGeom {
     int BX, BY, BN;      // raw-b region (ext+2)^3, origin o-1
 };
 
-template <typename R>
+// Geometry of tile T.  The LDS regions are laid out for the full tile shape
+// (1 << tshift per axis; ext only limits which cells hold particles), so with
+// FIX = 1 (every tile 4x4x4) all their strides are compile-time constants.
+template <typename R, int FIX = 0>
 __device__ inline TileGeom<R> tile_geom(const BoxDev<R> &B, int T)
 {
     TileGeom<R> g;
+    const int sx = FIX ? 2 : B.tshift[0], sy = FIX ? 2 : B.tshift[1], sz = FIX ? 2 : B.tshift[2];
     const int tx = T % B.ntile[0];
     const int r = T / B.ntile[0];
     const int ty = r % B.ntile[1], tz = r / B.ntile[1];
-    g.o[0] = tx << B.tshift[0];
-    g.o[1] = ty << B.tshift[1];
-    g.o[2] = tz << B.tshift[2];
-    for (int a = 0; a < 3; ++a) g.ext[a] = min(1 << B.tshift[a], B.n[a] - g.o[a]);
-    g.NX = g.ext[0] + 1; g.NY = g.ext[1] + 1; g.NN = g.NX * g.NY * (g.ext[2] + 1);
-    g.JX = g.ext[0] + 3; g.JY = g.ext[1] + 3; g.JN = g.JX * g.JY * (g.ext[2] + 3);
-    g.BX = g.ext[0] + 2; g.BY = g.ext[1] + 2; g.BN = g.BX * g.BY * (g.ext[2] + 2);
+    g.o[0] = tx << sx;
+    g.o[1] = ty << sy;
+    g.o[2] = tz << sz;
+    const int t0 = 1 << sx, t1 = 1 << sy, t2 = 1 << sz;
+    g.ext[0] = min(t0, B.n[0] - g.o[0]);
+    g.ext[1] = min(t1, B.n[1] - g.o[1]);
+    g.ext[2] = min(t2, B.n[2] - g.o[2]);
+    g.NX = t0 + 1; g.NY = t1 + 1; g.NN = g.NX * g.NY * (t2 + 1);
+    g.JX = t0 + 3; g.JY = t1 + 3; g.JN = g.JX * g.JY * (t2 + 3);
+    g.BX = t0 + 2; g.BY = t1 + 2; g.BN = g.BX * g.BY * (t2 + 2);
     return g;
 }
 
@@ -545,7 +552,7 @@ __device__ inline int move_bin(const TileGeom<R> &g, const TileRim &rim, const i
 template <typename R> struct PushWaves { static constexpr int value = 4; };
 template <> struct PushWaves<double> { static constexpr int value = 2; };
 
-template <typename R>
+template <typename R, int FIX>
 __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const BoxDev<R> *__restrict__ boxes,
                                                       const Item *__restrict__ items, StepConst<R> C);
 
@@ -604,7 +611,7 @@ __device__ void push_overflow(const BoxDev<R> &B, int kblk, const StepConst<R> &
 // FP32 form: four waves per SIMD (at most 128 VGPRs), the occupancy that
 // hides the latency of the LDS gather and of the particle loads best on
 // gfx950.  FP64 form: two (its doubled registers would spill at four).
-template <typename R>
+template <typename R, int FIX>
 __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const BoxDev<R> *__restrict__ boxes,
                                                       const Item *__restrict__ items, StepConst<R> C)
 {
@@ -618,12 +625,12 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     }
     const int T = it.tile;
     const int tid = threadIdx.x;
-    const TileGeom<R> g = tile_geom(B, T);
+    const TileGeom<R> g = tile_geom<R, FIX>(B, T);
     const TileRim rim = tile_rim(B, g);
     // LDS: per-cell trilinear coefficients | piece queues | union of {raw e,
     // raw b, node fields} (set-up) and the tile current (particle loop)
-    const int tsx = B.tshift[0], tsxy = B.tshift[0] + B.tshift[1];
-    const TileLds lds = tile_lds<R>(1 << B.tshift[0], 1 << B.tshift[1], 1 << B.tshift[2]);
+    const int tsx = FIX ? 2 : B.tshift[0], tsxy = FIX ? 4 : B.tshift[0] + B.tshift[1];
+    const TileLds lds = FIX ? tile_lds<R>(4, 4, 4) : tile_lds<R>(1 << B.tshift[0], 1 << B.tshift[1], 1 << B.tshift[2]);
     R *coef = reinterpret_cast<R *>(smem);
     unsigned char *qmem = smem + lds.coef;
     unsigned char *uni = qmem + lds.stage;
@@ -843,24 +850,19 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         const int dst = C.cur ^ 1;
         const int dst_start = __builtin_amdgcn_readfirstlane(S.seg_start[dst][T]);
         // the particle of the next iteration is loaded one iteration ahead, so
-        // that its HBM latency is covered by the work on the current one
-        const int32_t cell_pad = pack_cell(g.o[0], g.o[1], g.o[2]);
-        int32_t nx_cell = cell_pad, nx_id = 0;
+        // that its HBM latency is covered by the work on the current one;
+        // lanes past the end load the tile's last particle again and are
+        // masked out of every store, claim and deposit by `valid`
+        int32_t nx_cell = 0, nx_id = 0;
         R nx_d[3] = {R(0.5), R(0.5), R(0.5)}, nx_u[3] = {R(0), R(0), R(0)};
         auto fetch = [&](int q) {
-            if (q < n) {
-                const int at = src.slot(q);
-                nx_cell = slot_ref(P.cell, at);
-                nx_d[0] = slot_ref(P.d[0], at); nx_d[1] = slot_ref(P.d[1], at); nx_d[2] = slot_ref(P.d[2], at);
-                nx_u[0] = slot_ref(P.u[0], at); nx_u[1] = slot_ref(P.u[1], at); nx_u[2] = slot_ref(P.u[2], at);
-                if (P.id) nx_id = slot_ref(P.id, at);
-            } else {
-                nx_cell = cell_pad;
-                nx_d[0] = nx_d[1] = nx_d[2] = R(0.5);
-                nx_u[0] = nx_u[1] = nx_u[2] = R(0);
-            }
+            const int at = src.slot(min(q, n - 1));
+            nx_cell = slot_ref(P.cell, at);
+            nx_d[0] = slot_ref(P.d[0], at); nx_d[1] = slot_ref(P.d[1], at); nx_d[2] = slot_ref(P.d[2], at);
+            nx_u[0] = slot_ref(P.u[0], at); nx_u[1] = slot_ref(P.u[1], at); nx_u[2] = slot_ref(P.u[2], at);
+            if (P.id) nx_id = slot_ref(P.id, at);
         };
-        fetch(tid);
+        if (n > 0) fetch(tid);
         for (int pb = 0; pb < n; pb += kBlock) {
             const int p = pb + tid;
             const bool valid = p < n;
@@ -892,11 +894,14 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                 Bf[0] = F[3]; Bf[1] = F[4]; Bf[2] = F[5];
             }
             boris(hk, E, Bf, u);
-            if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]))) {
+            // one test catches NaN and infinity (and |u| beyond 1e15)
+            R u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            if (!(u2 < R(1e30))) {
                 if (valid) atomicOr(C.flags, PIC_FLAG_NONFINITE);
                 u[0] = u[1] = u[2] = R(0);
+                u2 = R(0);
             }
-            const R ig = C.dt * fast_rsqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            const R ig = C.dt * fast_rsqrt(R(1) + u2);
             R D[3] = {ig * u[0], ig * u[1], ig * u[2]};
             // D stays the rounded product (no multiply-add into x1 = d + D):
             // a queued move's crossings are recomputed from the stored (d, D)
@@ -1484,18 +1489,25 @@ size_t push_lds_bytes(int t0, int t1, int t2) { return tile_lds_bytes<R>(t0, t1,
 
 template <typename R>
 hipError_t launch_push(const BoxDev<R> *boxes, const Item *items, int nitems, size_t lds, const StepConst<R> &C,
-                       hipStream_t st)
+                       int fixed444, hipStream_t st)
 {
-    if (lds > 65536) {
-        static bool raised = false;
-        if (!raised) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&push_kernel<R>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-            raised = true;
-        }
+    // dynamic LDS beyond 64 KiB has to be allowed per kernel, once
+    auto allow = [&](const void *k, bool &done) -> hipError_t {
+        if (lds <= 65536 || done) return hipSuccess;
+        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e == hipSuccess) done = true;
+        return e;
+    };
+    static bool raised[2] = {false, false};
+    if (fixed444) {
+        const hipError_t e = allow(reinterpret_cast<const void *>(&push_kernel<R, 1>), raised[1]);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((push_kernel<R, 1>), dim3(nitems), dim3(kBlock), lds, st, boxes, items, C);
+    } else {
+        const hipError_t e = allow(reinterpret_cast<const void *>(&push_kernel<R, 0>), raised[0]);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((push_kernel<R, 0>), dim3(nitems), dim3(kBlock), lds, st, boxes, items, C);
     }
-    hipLaunchKernelGGL(push_kernel<R>, dim3(nitems), dim3(kBlock), lds, st, boxes, items, C);
     return hipGetLastError();
 }
 
@@ -1548,7 +1560,7 @@ hipError_t launch_diag(const BoxDev<R> *boxes, int box, int64_t nc, const Item *
 #define PIC_INSTANTIATE(R)                                                                                     \
     template size_t push_lds_bytes<R>(int, int, int);                                                         \
     template hipError_t launch_push<R>(const BoxDev<R> *, const Item *, int, size_t, const StepConst<R> &,   \
-                                       hipStream_t);                                                          \
+                                       int, hipStream_t);                                                     \
     template hipError_t launch_fields<R>(const BoxDev<R> *, const CellBlock *, int, R, int, int, int,          \
                                          hipStream_t);                                                        \
     template hipError_t launch_advance_b<R>(const BoxDev<R> *, const CellBlock *, int, R, hipStream_t);       \

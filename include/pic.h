@@ -259,6 +259,19 @@ int pic_free(pic_ctx *ctx);
 /* Message of the last error on ctx (static storage of the context). */
 const char *pic_last_error(const pic_ctx *ctx);
 
+/*
+ * Fourier power spectrum of one field component in the planes normal to
+ * `normal_axis`, summed over those planes (Sect. 3.2.2, method of
+ * measurement): PS(m1, m2) = sum_p |sum_{i1,i2} f(i1, i2, p)
+ * exp(-2 pi i (m1 i1 / N1 + m2 i2 / N2))|^2, where (a1, a2) are the two other
+ * axes in increasing order, N1 = n[a1], N2 = n[a2], and f is e^t (field 0) or
+ * b^t = b^{t-dt/2} - (dt/2) curl e^t (field 1), component comp, at its Yee
+ * position.  FP64.  ps: caller's host array of N1 * N2 doubles, mode (m1, m2)
+ * at ps[m1 + N1 m2] for m1 in [0, N1), m2 in [0, N2) (the paper samples
+ * m1 <= N1/2, m2 <= N2/2).  Synchronises.
+ */
+int pic_field_spectrum(pic_ctx *ctx, int box, int field, int comp, int normal_axis, double *ps);
+
 /* Outcome of pic_autotune. */
 typedef struct pic_tune_result {
     double  ms_per_step;          /* time per step of the chosen configuration */

@@ -146,6 +146,19 @@ def filter27(dims, f):
     return f
 
 
+def plane_power_spectrum(dims, f, normal):
+    """Power spectrum of a field component in the planes normal to axis
+    `normal`, summed over the planes (Sect. 3.2.2, method of measurement):
+    the 2-D DFT over the two other axes (a1 < a2) of each plane, |.|^2, summed
+    over planes.  f: one component grid, index i + n0 (j + n1 k).  Returns
+    an array [m2, m1].  The DFT is numpy's FFT."""
+    F = np.asarray(f, dtype=np.float64).reshape(dims[2], dims[1], dims[0])
+    ax = {0: 2, 1: 1, 2: 0}                     # grid axis -> array axis
+    a1, a2 = [a for a in range(3) if a != normal]
+    G = np.transpose(F, (ax[normal], ax[a2], ax[a1]))
+    return (np.abs(np.fft.fft2(G, axes=(1, 2))) ** 2).sum(axis=0)
+
+
 def deposit_charge(dims, sgn, x, rho=None):
     """CIC node weights of a particle at x (App. A.3.3)."""
     rho = np.zeros(int(np.prod(dims))) if rho is None else rho

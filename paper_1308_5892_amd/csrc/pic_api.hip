@@ -586,6 +586,33 @@ int pic_diag(pic_ctx *ctx, int box, pic_diag_out *out, int64_t *hist)
 }
 
 template <typename R>
+static int spectrum_t(pic_ctx *ctx, int box, int field, int comp, int normal, double *ps)
+{
+    const BoxDev<R> &D = bdvec<R>(ctx)[box];
+    const BoxDev<R> *boxes = reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes);
+    const int a1 = normal == 0 ? 1 : 0, a2 = normal == 2 ? 1 : 2;
+    const size_t nps = (size_t)D.n[a1] * D.n[a2];
+    // scratch: the box's current (cleared between steps) and its diagnostic charge array
+    HIPCHK(launch_spectrum<R>(boxes, box, D.n, field, comp, normal, (R)(0.5 * ctx->cfg.dt),
+                              reinterpret_cast<double *>(D.J), D.rho, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ps, D.rho, nps * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return PIC_OK;
+}
+
+int pic_field_spectrum(pic_ctx *ctx, int box, int field, int comp, int normal_axis, double *ps)
+{
+    int rc = check_box(ctx, box);
+    if (rc) return rc;
+    if (field < 0 || field > 1 || comp < 0 || comp > 2 || normal_axis < 0 || normal_axis > 2 || !ps)
+        return PIC_EINVAL;
+    rc = merge(ctx);
+    if (rc) return rc;
+    return ctx->fp64 ? spectrum_t<double>(ctx, box, field, comp, normal_axis, ps)
+                     : spectrum_t<float>(ctx, box, field, comp, normal_axis, ps);
+}
+
+template <typename R>
 static int get_particles_t(pic_ctx *ctx, int box, int s, double *x, double *u, int32_t *id, int64_t *n)
 {
     const BoxDev<R> &D = bdvec<R>(ctx)[box];

@@ -189,5 +189,8 @@ hipError_t launch_mj_table(double theta, double gamma_beta, double *cum, int M, 
 template <typename R> hipError_t launch_load_pairs(const BoxDev<R> *boxes, const LoadArgs &L, hipStream_t st);
 template <typename R>
 hipError_t launch_harris_field(const BoxDev<R> *boxes, int64_t nc, const pic_harris_field &H, hipStream_t st);
+template <typename R>
+hipError_t launch_spectrum(const BoxDev<R> *boxes, int box, const int n[3], int f, int c, int an, R hdt,
+                           double *scratch, double *ps, hipStream_t st);
 
 } // namespace pic

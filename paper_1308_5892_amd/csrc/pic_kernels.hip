@@ -1557,6 +1557,119 @@ hipError_t launch_diag(const BoxDev<R> *boxes, int box, int64_t nc, const Item *
     return hipGetLastError();
 }
 
+// ------------------------------------------------- field Fourier spectra
+
+// Value of field f (0: e^t, 1: b^t = b^{t-dt/2} - (dt/2) curl e^t), component
+// c, at grid point (x[0], x[1], x[2]).
+template <typename R>
+__device__ inline double field_at(const BoxDev<R> &B, int f, int c, const int x[3], R hdt)
+{
+    if (f == 0) return (double)B.e[c * B.nc + x[0] + (int64_t)B.n[0] * (x[1] + (int64_t)B.n[1] * x[2])];
+    return (double)bt_global(B, c, x[0], x[1], x[2], hdt);
+}
+
+// First pass of the plane spectra (Sect. 3.2.2): for every plane normal to
+// axis an and every line along axis a2 of it, the DFT along axis a1,
+// tmp[(p * N2 + i2) * N1 + m1] = sum_i1 f(i1, i2, p) exp(-2 pi i m1 i1 / N1),
+// in FP64.  One thread per output value; the block stages the N1 twiddle
+// factors in LDS.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) spectrum_rows_kernel(const BoxDev<R> *__restrict__ boxes, int box,
+                                                               int f, int c, int a1, int a2, int an, R hdt,
+                                                               double2 *__restrict__ tmp)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *w = reinterpret_cast<double2 *>(smem);
+    const BoxDev<R> &B = boxes[box];
+    const int N1 = B.n[a1], N2 = B.n[a2], NP = B.n[an];
+    for (int q = threadIdx.x; q < N1; q += kBlock) {
+        double sn, cs;
+        sincospi(-2.0 * q / N1, &sn, &cs);
+        w[q] = make_double2(cs, sn);
+    }
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)N1 * N2 * NP) return;
+    const int m1 = (int)(t % N1);
+    const int64_t r = t / N1;
+    const int i2 = (int)(r % N2), p = (int)(r / N2);
+    int x[3];
+    x[a2] = i2;
+    x[an] = p;
+    double re = 0.0, im = 0.0;
+    int k = 0;                                    // (m1 * i1) mod N1
+    for (int i1 = 0; i1 < N1; ++i1) {
+        x[a1] = i1;
+        const double v = field_at(B, f, c, x, hdt);
+        re += v * w[k].x;
+        im += v * w[k].y;
+        k += m1;
+        if (k >= N1) k -= N1;
+    }
+    tmp[t] = make_double2(re, im);
+}
+
+// Second pass: the DFT along a2 and the power summed over the planes,
+// ps[m1 + N1 m2] = sum_p |sum_i2 tmp[(p N2 + i2) N1 + m1] exp(-2 pi i m2 i2 / N2)|^2.
+template <typename R>
+__global__ void __launch_bounds__(kBlock) spectrum_cols_kernel(const BoxDev<R> *__restrict__ boxes, int box,
+                                                               int a1, int a2, int an,
+                                                               const double2 *__restrict__ tmp,
+                                                               double *__restrict__ ps)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *w = reinterpret_cast<double2 *>(smem);
+    const BoxDev<R> &B = boxes[box];
+    const int N1 = B.n[a1], N2 = B.n[a2], NP = B.n[an];
+    for (int q = threadIdx.x; q < N2; q += kBlock) {
+        double sn, cs;
+        sincospi(-2.0 * q / N2, &sn, &cs);
+        w[q] = make_double2(cs, sn);
+    }
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)N1 * N2) return;
+    const int m1 = (int)(t % N1), m2 = (int)(t / N1);
+    double pw = 0.0;
+    for (int p = 0; p < NP; ++p) {
+        double re = 0.0, im = 0.0;
+        int k = 0;                                // (m2 * i2) mod N2
+        for (int i2 = 0; i2 < N2; ++i2) {
+            const double2 a = tmp[((int64_t)p * N2 + i2) * N1 + m1];
+            re += a.x * w[k].x - a.y * w[k].y;
+            im += a.x * w[k].y + a.y * w[k].x;
+            k += m2;
+            if (k >= N2) k -= N2;
+        }
+        pw += re * re + im * im;
+    }
+    ps[t] = pw;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) fill_zero_kernel(double *__restrict__ p, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < n) p[t] = 0.0;
+}
+
+template <typename R>
+hipError_t launch_spectrum(const BoxDev<R> *boxes, int box, const int n[3], int f, int c, int an, R hdt,
+                           double *scratch, double *ps, hipStream_t st)
+{
+    const int a1 = an == 0 ? 1 : 0, a2 = an == 2 ? 1 : 2;
+    const int64_t rows = (int64_t)n[a1] * n[a2] * n[an], cols = (int64_t)n[a1] * n[a2];
+    double2 *tmp = reinterpret_cast<double2 *>(scratch);
+    hipLaunchKernelGGL(spectrum_rows_kernel<R>, dim3((unsigned)((rows + kBlock - 1) / kBlock)), dim3(kBlock),
+                       n[a1] * sizeof(double2), st, boxes, box, f, c, a1, a2, an, hdt, tmp);
+    hipLaunchKernelGGL(spectrum_cols_kernel<R>, dim3((unsigned)((cols + kBlock - 1) / kBlock)), dim3(kBlock),
+                       n[a2] * sizeof(double2), st, boxes, box, a1, a2, an, (const double2 *)tmp, ps);
+    // the scratch is the current buffer of the box, which the next push expects cleared
+    hipLaunchKernelGGL(fill_zero_kernel<R>, dim3((unsigned)((2 * rows + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       st, scratch, 2 * rows);
+    return hipGetLastError();
+}
+
 #define PIC_INSTANTIATE(R)                                                                                     \
     template size_t push_lds_bytes<R>(int, int, int);                                                         \
     template hipError_t launch_push<R>(const BoxDev<R> *, const Item *, int, size_t, const StepConst<R> &,   \
@@ -1567,7 +1680,9 @@ hipError_t launch_diag(const BoxDev<R> *boxes, int box, int64_t nc, const Item *
     template hipError_t launch_repack<R>(const BoxDev<R> *, int, const Item *, int, const StageItem *, int,    \
                                          const StepConst<R> &, hipStream_t);                                  \
     template hipError_t launch_diag<R>(const BoxDev<R> *, int, int64_t, const Item *, int,                    \
-                                       const StepConst<R> &, hipStream_t);
+                                       const StepConst<R> &, hipStream_t);                                    \
+    template hipError_t launch_spectrum<R>(const BoxDev<R> *, int, const int[3], int, int, int, R, double *,   \
+                                           double *, hipStream_t);
 
 PIC_INSTANTIATE(float)
 PIC_INSTANTIATE(double)

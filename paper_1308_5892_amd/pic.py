@@ -26,7 +26,7 @@ ERROR_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ECOURANT", -3: "PIC_ENOME
 EXPORTED = ["pic_plan", "pic_init", "pic_load_maxwell_juttner", "pic_set_harris_field", "pic_step",
             "pic_diag", "pic_get_particles", "pic_set_particles", "pic_get_fields", "pic_set_fields",
             "pic_sync", "pic_steps_done", "pic_free", "pic_last_error", "pic_set_timing",
-            "pic_get_timing", "pic_autotune"]
+            "pic_get_timing", "pic_autotune", "pic_field_spectrum"]
 
 
 class pic_species(C.Structure):
@@ -116,6 +116,7 @@ def lib():
         L.pic_last_error.restype = C.c_char_p
         L.pic_set_timing.argtypes = [C.c_void_p, C.c_int]
         L.pic_get_timing.argtypes = [C.c_void_p, C.POINTER(pic_timing), C.c_int]
+        L.pic_field_spectrum.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p]
         L.pic_autotune.argtypes = [C.POINTER(pic_config), C.POINTER(pic_load_desc), C.c_int, C.c_void_p, C.c_size_t,
                                    C.c_void_p, C.c_int, C.POINTER(pic_config), C.POINTER(pic_box),
                                    C.POINTER(pic_tune_result)]
@@ -251,6 +252,14 @@ def pic_get_timing(ctx, reset=True):
             "field_ms": t.field_ms, "sort_launches": t.sort_launches, "sort_ms": t.sort_ms}
 
 
+def pic_field_spectrum(ctx, box, n, field, comp, normal_axis):
+    """Plane-summed power spectrum as an (N2, N1) array: [m2, m1]."""
+    a1, a2 = [a for a in range(3) if a != normal_axis]
+    ps = np.zeros(n[a1] * n[a2])
+    _check(lib().pic_field_spectrum(ctx, int(box), int(field), int(comp), int(normal_axis), _ptr(ps)), ctx)
+    return ps.reshape(n[a2], n[a1])
+
+
 def pic_autotune(cfg, loads, arena_ptr, nbytes, stream_ptr, steps):
     """Returns (tuned pic_config, its pic_box array, pic_tune_result)."""
     arr = (pic_load_desc * max(1, len(loads)))(*loads)
@@ -360,6 +369,9 @@ class Simulation:
 
     def fields(self, box=0):
         return pic_get_fields(self.ctx, box, self.ncells(box))
+
+    def spectrum(self, box=0, field=1, comp=1, normal_axis=1):
+        return pic_field_spectrum(self.ctx, box, self.boxes[box]["n"], field, comp, normal_axis)
 
     def set_fields(self, box=0, e=None, b=None):
         pic_set_fields(self.ctx, box, e, b)

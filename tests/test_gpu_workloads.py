@@ -375,3 +375,34 @@ def test_autotune_picks_a_working_configuration():
         assert d["flags"] == 0
         assert d["count"].tolist() == [bx["ppc"] * int(np.prod(bx["dims"]))] * 2
     sim.close()
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_plane_spectra_match_oracle_and_leave_the_step_intact(fp64):
+    from oracle import oracle as O
+    rng = np.random.default_rng(17)
+    dims = (12, 10, 6)
+    n = int(np.prod(dims))
+    npart = 3000
+    s = G.sim(dims, 10.0, 16.0, [npart, npart], fp64=fp64)
+    st = G.oracle_state(dims, 10.0, 16.0)
+    e, b = G.random_fields(rng, n, 0.05, 0.3)
+    parts = []
+    for _ in range(2):
+        x = rng.uniform(0, 1, (npart, 3)) * np.array(dims)
+        parts.append((x, 0.4 * rng.standard_normal((npart, 3))))
+    G.start(s, st, parts, e=e, b=b, fp64=fp64)
+    bt = O.advance_b(dims, 0.5 * st.dt, st.e, st.b)
+    for field, src in ((0, st.e), (1, bt)):
+        for comp in range(3):
+            for normal in range(3):
+                got = s.spectrum(0, field, comp, normal)
+                ref = O.plane_power_spectrum(dims, src[comp * n:(comp + 1) * n], normal)
+                tol = (1e-12 if fp64 or field == 0 else 1e-6) * ref.max()
+                assert np.abs(got - ref).max() <= tol, (field, comp, normal)
+    # the spectra borrow the current buffer: the next step is unaffected
+    s.step(1)
+    st.step(1)
+    e1, _, _ = s.fields(0)
+    assert np.abs(e1 - st.e).max() < (1e-12 if fp64 else 2e-6) * np.abs(st.e).max()
+    s.close()

@@ -192,8 +192,15 @@ int pic_load_maxwell_juttner(pic_ctx *ctx, const pic_load_desc *d);
 int pic_set_harris_field(pic_ctx *ctx, const pic_harris_field *h);
 
 /*
- * Enqueue n full cycles of App. A.3.1 on the stream for every box.  Does not
- * synchronise; kernel faults surface in the next pic_diag / pic_sync.
+ * Enqueue n full cycles of App. A.3.1 on the stream for every box.  Kernel
+ * faults surface in the next pic_diag / pic_sync.  Particles are re-binned
+ * every sort_interval steps, and also as soon as an overflow region (the
+ * slow path for particles whose tile segment is full) is half full, or holds
+ * more than 8192 particles:
+ * after each step a small kernel reports the fullest one, and pic_step reads
+ * that report two steps later, so it keeps the stream at most two steps ahead
+ * of the host instead of returning at once.  Uses pinned host memory (a few
+ * bytes) allocated by pic_init.
  */
 int pic_step(pic_ctx *ctx, int n);
 

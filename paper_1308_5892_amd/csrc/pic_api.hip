@@ -202,6 +202,15 @@ static void make_layout(const pic_config *cfg, std::vector<BoxHost> &bh, char *b
 
 using namespace pic;
 
+// Overflow watch: after every step a one-block kernel writes the fill of the
+// fullest overflow region (thousandths of its capacity) to a device word that
+// is copied to pinned host memory; pic_step reads it kWatchLag steps later
+// (waiting for that step only, so the stream stays kWatchLag steps ahead) and
+// repacks at once when the fill is above kWatchLimit, instead of letting the
+// overflow region - swept by the slow path - fill up or lose particles.
+constexpr int kWatch = 4, kWatchLag = 2;
+constexpr uint32_t kWatchLimit = 500;
+
 struct pic_ctx {
     pic_config cfg;
     std::vector<pic_box> boxes;
@@ -226,11 +235,19 @@ struct pic_ctx {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
     std::vector<hipEvent_t> ev_pool;
+    uint32_t *watch_host = nullptr;          // pinned, kWatch slots
+    hipEvent_t watch_ev[kWatch] = {};
+    int64_t watch_step[kWatch] = {-1, -1, -1, -1};
+    int64_t last_repack = 0;
+    int64_t early_repacks = 0;
     ~pic_ctx()
     {
         for (auto &v : ev)
             for (auto &p : v) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
         for (auto e : ev_pool) hipEventDestroy(e);
+        for (auto e : watch_ev)
+            if (e) hipEventDestroy(e);
+        if (watch_host) hipHostFree(watch_host);
     }
 };
 
@@ -432,6 +449,16 @@ int pic_init(const pic_config *cfg, void *dev_arena, size_t bytes, void *hip_str
     ctx->stage_n.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
     ctx->stage_half.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
     ctx->next_id.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
+    if (hipHostMalloc(reinterpret_cast<void **>(&ctx->watch_host), kWatch * sizeof(uint32_t)) != hipSuccess) {
+        ctx->watch_host = nullptr;
+        delete ctx;
+        return PIC_EDEVICE;
+    }
+    for (auto &e : ctx->watch_ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            delete ctx;
+            return PIC_EDEVICE;
+        }
     rc = ctx->fp64 ? init_t<double>(ctx) : init_t<float>(ctx);
     if (rc) {
         fprintf(stderr, "pic_init: %s\n", ctx->err.c_str());
@@ -492,6 +519,19 @@ static int step_t(pic_ctx *ctx, int n)
 {
     const BoxDev<R> *boxes = reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes);
     for (int i = 0; i < n; ++i) {
+        // early repack when the overflow watch of kWatchLag steps ago says so
+        const int64_t look = ctx->step - kWatchLag;
+        if (look > ctx->last_repack && ctx->watch_step[look % kWatch] == look) {
+            HIPCHK(hipEventSynchronize(ctx->watch_ev[look % kWatch]));
+            if (ctx->watch_host[look % kWatch] > kWatchLimit) {
+                mark(ctx, 2, true);
+                int rc = merge_t<R>(ctx, true);
+                mark(ctx, 2, false);
+                if (rc) return rc;
+                ctx->last_repack = ctx->step;
+                ctx->early_repacks += 1;
+            }
+        }
         StepConst<R> C = step_const<R>(ctx);
         mark(ctx, 0, true);
         HIPCHK(launch_push<R>(boxes, ctx->L.items_push, ctx->L.n_items, ctx->lds_bytes, C, ctx->fixed444 ? 1 : 0,
@@ -503,11 +543,21 @@ static int step_t(pic_ctx *ctx, int n)
         mark(ctx, 1, false);
         ctx->cur ^= 1;
         ctx->step += 1;
+        {
+            const int w = (int)(ctx->step % kWatch);
+            HIPCHK(launch_overflow_watch<R>(boxes, ctx->cfg.n_boxes, ctx->cfg.n_species, ctx->cur, ctx->L.flags + 8,
+                                            ctx->stream));
+            HIPCHK(hipMemcpyAsync(ctx->watch_host + w, ctx->L.flags + 8, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+            HIPCHK(hipEventRecord(ctx->watch_ev[w], ctx->stream));
+            ctx->watch_step[w] = ctx->step;
+        }
         if (ctx->cfg.sort_interval > 0 && ctx->step % ctx->cfg.sort_interval == 0) {
             mark(ctx, 2, true);
             int rc = merge_t<R>(ctx, true);
             mark(ctx, 2, false);
             if (rc) return rc;
+            ctx->last_repack = ctx->step;
         }
     }
     return PIC_OK;

@@ -40,7 +40,7 @@
 namespace pic {
 
 constexpr int kMaxSpecies = PIC_MAX_SPECIES;
-constexpr int kOvfBlocks = 4;      // blocks per box sweeping the overflow region
+constexpr int kOvfBlocks = 16;     // blocks per box sweeping the overflow region
 constexpr int kBlock = 256;        // threads per block of the particle kernels
 constexpr int kQBits = 31;         // fractional bits of the fixed-point current
 
@@ -189,6 +189,9 @@ hipError_t launch_mj_table(double theta, double gamma_beta, double *cum, int M, 
 template <typename R> hipError_t launch_load_pairs(const BoxDev<R> *boxes, const LoadArgs &L, hipStream_t st);
 template <typename R>
 hipError_t launch_harris_field(const BoxDev<R> *boxes, int64_t nc, const pic_harris_field &H, hipStream_t st);
+template <typename R>
+hipError_t launch_overflow_watch(const BoxDev<R> *boxes, int nboxes, int nsp, int copy, uint32_t *out,
+                                 hipStream_t st);
 template <typename R>
 hipError_t launch_spectrum(const BoxDev<R> *boxes, int box, const int n[3], int f, int c, int an, R hdt,
                            double *scratch, double *ps, hipStream_t st);

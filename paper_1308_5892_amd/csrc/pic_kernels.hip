@@ -1557,6 +1557,43 @@ hipError_t launch_diag(const BoxDev<R> *boxes, int box, int64_t nc, const Item *
     return hipGetLastError();
 }
 
+// ------------------------------------------------------ overflow watch
+
+// Fill of the fullest overflow region after a push, over every box and
+// species of copy `copy` (the one just written), in thousandths of the smaller
+// of its capacity and kOvfBlocks * 1024 particles (the load its sweep blocks
+// take in four rounds).
+template <typename R>
+__global__ void __launch_bounds__(kBlock) overflow_watch_kernel(const BoxDev<R> *__restrict__ boxes, int nboxes,
+                                                                int nsp, int copy, uint32_t *__restrict__ out)
+{
+    __shared__ unsigned int best;
+    if (threadIdx.x == 0) best = 0;
+    __syncthreads();
+    unsigned int m = 0;
+    for (int b = threadIdx.x; b < nboxes; b += kBlock) {
+        const BoxDev<R> &B = boxes[b];
+        for (int s = 0; s < nsp; ++s) {
+            const SpeciesDev<R> &S = B.sp[s];
+            const long long c = S.nb[copy][B.ntiles];
+            const long long cap = min((long long)S.ovf_cap, (long long)kOvfBlocks * 1024);
+            const unsigned int f = (unsigned int)min(1000LL, c * 1000LL / max(1LL, cap));
+            m = max(m, f);
+        }
+    }
+    atomicMax(&best, m);
+    __syncthreads();
+    if (threadIdx.x == 0) *out = best;
+}
+
+template <typename R>
+hipError_t launch_overflow_watch(const BoxDev<R> *boxes, int nboxes, int nsp, int copy, uint32_t *out,
+                                 hipStream_t st)
+{
+    hipLaunchKernelGGL(overflow_watch_kernel<R>, dim3(1), dim3(kBlock), 0, st, boxes, nboxes, nsp, copy, out);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------- field Fourier spectra
 
 // Value of field f (0: e^t, 1: b^t = b^{t-dt/2} - (dt/2) curl e^t), component
@@ -1682,7 +1719,8 @@ hipError_t launch_spectrum(const BoxDev<R> *boxes, int box, const int n[3], int 
     template hipError_t launch_diag<R>(const BoxDev<R> *, int, int64_t, const Item *, int,                    \
                                        const StepConst<R> &, hipStream_t);                                    \
     template hipError_t launch_spectrum<R>(const BoxDev<R> *, int, const int[3], int, int, int, R, double *,   \
-                                           double *, hipStream_t);
+                                           double *, hipStream_t);                                            \
+    template hipError_t launch_overflow_watch<R>(const BoxDev<R> *, int, int, int, uint32_t *, hipStream_t);
 
 PIC_INSTANTIATE(float)
 PIC_INSTANTIATE(double)

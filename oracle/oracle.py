@@ -55,12 +55,13 @@ def lib():
         L.orc_deposit_move.restype = C.c_int
         L.orc_deposit_charge.argtypes = [G, C.c_double, _dp, _dp]
         L.orc_step.argtypes = [G, C.c_double, C.c_double, C.c_int, _dp, _dp, C.c_int64,
-                               _ip, _dp, _dp, _dp, _dp, C.c_int, C.c_int]
+                               _ip, _dp, _dp, _dp, _dp, C.c_int, C.c_int, C.c_int]
         L.orc_filter27.argtypes = [G, C.c_int, _dp]
+        L.orc_wall_fields.argtypes = [G, C.c_int, _dp, _dp]
         L.orc_backward_half.argtypes = [G, C.c_double, _dp, C.c_int64, _ip, _dp, _dp, _dp, _dp]
         L.orc_diag.argtypes = [G, C.c_double, C.c_double, C.c_int, _dp, _dp, _dp, C.c_int64,
                                _ip, _dp, _dp, _dp, _dp, _dp, C.c_int, C.c_double, C.c_double,
-                               C.c_void_p, C.c_int]
+                               C.c_void_p, C.c_int, C.c_int]
         L.orc_philox4x64.argtypes = [_up, _up, _up]
         L.orc_mj_range.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_mj_table.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, _dp]
@@ -138,6 +139,13 @@ def deposit_move(dims, sgn, x0, x1, J=None):
     return J, npieces
 
 
+def wall_fields(dims, wall, e, b):
+    """Conducting-wall condition (App. A.4) on the wall plane of axis `wall`."""
+    e, b = _f(e).copy(), _f(b).copy()
+    lib().orc_wall_fields(_g(dims), int(wall), e, b)
+    return e, b
+
+
 def filter27(dims, f):
     """The 27-point current smoothing of App. A.3.4 on each component grid."""
     f = _f(f).copy()
@@ -187,6 +195,7 @@ class State:
         self.u = np.zeros((0, 3))
         self.species = np.zeros(0, dtype=np.int32)
         self.filter = False                      # smooth the current (App. A.3.4)
+        self.wall = -1                           # axis with conducting walls (App. A.4), -1: none
 
     def add_particles(self, s, x, u):
         self.x = np.concatenate([self.x, _f(x).reshape(-1, 3)])
@@ -199,7 +208,7 @@ class State:
         u = np.ascontiguousarray(self.u).reshape(-1)
         lib().orc_step(_g(self.dims), self.dt, self.alpha0, len(self.kq), self.kq, self.sgn,
                        len(self.species), np.ascontiguousarray(self.species), x, u,
-                       self.e, self.b, int(nsteps), int(self.filter))
+                       self.e, self.b, int(nsteps), int(self.filter), int(self.wall))
         self.x = x.reshape(-1, 3)
         self.u = u.reshape(-1, 3)
 
@@ -225,7 +234,7 @@ class State:
         lib().orc_diag(_g(self.dims), self.dt, self.alpha0, nsp, self.kq, self.sgn, self.m,
                        len(self.species), np.ascontiguousarray(self.species), x, u,
                        self.e, self.b, out, int(nbins), float(lo), float(hi),
-                       hist.ctypes.data if nbins > 0 else None, int(self.filter))
+                       hist.ctypes.data if nbins > 0 else None, int(self.filter), int(self.wall))
         d = {
             "W_E": out[0:3].copy(), "W_B": out[3:6].copy(),
             "gauss_max": out[6], "gauss_rms": out[7],

@@ -352,6 +352,28 @@ static double wrapd(double x, int n)
 }
 
 /*
+ * Perfectly conducting walls at the two box faces normal to axis w (App. A.4:
+ * the normal b and the tangential e vanish at a conductor's surface).  Both
+ * faces lie on the node plane of index 0 along w (index N wraps onto it), so
+ * the condition is: b_w = 0 and e_c = 0 (c != w) on that plane.  The Yee
+ * values there are then never used across the wall.
+ */
+void orc_wall_fields(const int g[3], int w, double *e, double *b)
+{
+    int64_t n = ncells(g);
+    for (int k = 0; k < g[2]; ++k)
+        for (int j = 0; j < g[1]; ++j)
+            for (int i = 0; i < g[0]; ++i) {
+                int idx[3] = {i, j, k};
+                if (idx[w] != 0) continue;
+                int64_t p = cell_index(g, i, j, k);
+                b[w * n + p] = 0.0;
+                for (int c = 0; c < 3; ++c)
+                    if (c != w) e[c * n + p] = 0.0;
+            }
+}
+
+/*
  * Smoothing of the current (App. A.3.4, last paragraph): each value of a grid
  * becomes the weighted sum of the 27 values around it - weight 1 for itself,
  * 1/2 for its 6 face neighbours, 1/4 for its 12 edge neighbours, 1/8 for its 8
@@ -387,21 +409,26 @@ void orc_filter27(const int g[3], int ncomp, double *f)
  * b at t - dt/2; on return they have advanced by nsteps*dt.
  * Particles: x[3p..3p+2] in [0, N), u likewise, species[p] in [0, nsp).
  * kq[s] = (q_s/e)(m_e/m_s), sgn[s] = sgn(q_s), alpha0 = 2/(n_x^2 rho0).
- * filter != 0 smooths the current (orc_filter27) before it enters e; every
- * boundary is periodic.
+ * filter != 0 smooths the current (orc_filter27) before it enters e.
+ * wall in {0, 1, 2} puts perfectly conducting walls at the two box faces
+ * normal to that axis (App. A.4; see orc_wall_fields and the move below);
+ * wall = -1: every boundary is periodic.
  */
 void orc_step(const int g[3], double dt, double alpha0, int nsp,
               const double *kq, const double *sgn, int64_t np,
               const int32_t *species, double *x, double *u,
-              double *e, double *b, int nsteps, int filter)
+              double *e, double *b, int nsteps, int filter, int wall)
 {
     int64_t n = ncells(g);
     double *J = (double *)malloc(sizeof(double) * 3 * n);
     double *xold = (double *)malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
     (void)nsp;
+    double *xwall = (double *)malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
+    char *hit = (char *)calloc((size_t)(np > 0 ? np : 1), 1);
     for (int it = 0; it < nsteps; ++it) {
         /* 1. b^{t-dt/2} -> b^t */
         orc_advance_b(g, 0.5 * dt, e, b);
+        if (wall >= 0) orc_wall_fields(g, wall, e, b);
         /* 2-3. velocity with e^t, b^t at x^t; then position to t+dt */
         for (int64_t p = 0; p < np; ++p) {
             double E[3], B[3];
@@ -410,30 +437,63 @@ void orc_step(const int g[3], double dt, double alpha0, int nsp,
             orc_boris(kq[s], dt, E, B, &u[3 * p]);
             double *up = &u[3 * p];
             double ig = 1.0 / sqrt(1.0 + up[0] * up[0] + up[1] * up[1] + up[2] * up[2]);
+            double D[3];
             for (int a = 0; a < 3; ++a) {
                 xold[3 * p + a] = x[3 * p + a];
-                x[3 * p + a] += dt * up[a] * ig;
+                D[a] = dt * up[a] * ig;
+                x[3 * p + a] += D[a];
+            }
+            hit[p] = 0;
+            if (wall >= 0) {
+                /* READING of the particle reflection (App. A.4): a move that
+                 * leaves through a wall is cut where it meets the wall; the rest
+                 * of it is mirrored back into the box and the normal momentum
+                 * changes sign.  The current is that of the two straight
+                 * pieces. */
+                double *xp = &x[3 * p];
+                double N = g[wall], xw = xp[wall];
+                if (xw < 0.0 || xw >= N) {
+                    double plane = xw < 0.0 ? 0.0 : N;
+                    double lam = (plane - xold[3 * p + wall]) / D[wall];
+                    for (int a = 0; a < 3; ++a) xwall[3 * p + a] = xold[3 * p + a] + lam * D[a];
+                    xwall[3 * p + wall] = plane;
+                    double xr = 2.0 * plane - xw;
+                    if (xr >= N) xr = nextafter(N, 0.0);   /* a move ending on the upper wall */
+                    xp[wall] = xr;
+                    up[wall] = -up[wall];
+                    hit[p] = 1;
+                }
             }
         }
         /* 4. b^t -> b^{t+dt/2} */
         orc_advance_b(g, 0.5 * dt, e, b);
+        if (wall >= 0) orc_wall_fields(g, wall, e, b);
         /* 6. e^t -> e^{t+dt} with curl b^{t+dt/2} */
         orc_advance_e(g, dt, b, e);
         /* 9. currents from the moves x^t -> x^{t+dt} (READING: the appendix's
          *    old position plus displacement, not item 9's wording) */
         memset(J, 0, sizeof(double) * 3 * n);
-        for (int64_t p = 0; p < np; ++p)
-            orc_deposit_move(g, sgn[species[p]], &xold[3 * p], &x[3 * p], J);
+        for (int64_t p = 0; p < np; ++p) {
+            if (hit[p]) {
+                orc_deposit_move(g, sgn[species[p]], &xold[3 * p], &xwall[3 * p], J);
+                orc_deposit_move(g, sgn[species[p]], &xwall[3 * p], &x[3 * p], J);
+            } else {
+                orc_deposit_move(g, sgn[species[p]], &xold[3 * p], &x[3 * p], J);
+            }
+        }
         /* 10. optional smoothing of the current (App. A.3.4) */
         if (filter) orc_filter27(g, 3, J);
         /* 12. e += alpha0 * sum_s sgn_s dV  (App. A.2, eq. max2bis) */
         for (int64_t q = 0; q < 3 * n; ++q)
             e[q] += alpha0 * J[q];
+        if (wall >= 0) orc_wall_fields(g, wall, e, b);
         /* 8. periodic particle boundary */
         for (int64_t p = 0; p < np; ++p)
             for (int a = 0; a < 3; ++a)
                 x[3 * p + a] = wrapd(x[3 * p + a], g[a]);
     }
+    free(hit);
+    free(xwall);
     free(xold);
     free(J);
 }
@@ -463,7 +523,8 @@ void orc_backward_half(const int g[3], double dt, const double *kq, int64_t np,
  *   [3..5]  W_B,c = (1/alpha0) sum 1/2 (b^t)_c^2, b^t = b - (dt/2) curl e
  *   [6]     max |div e - rho|,  [7] rms of the same,
  *           rho = alpha0 sum_s sgn_s sum_p W(x_p), smoothed like the
- *           current when filter != 0
+ *           current when filter != 0; with walls (wall >= 0) the nodes on
+ *           the wall plane (the conductor's surface charge) are left out
  *   then per species s (8 + 6 s): K_s = sum (m_s/m_e)(gamma^t - 1),
  *           P_s[3] = sum u^-, count, sum (gamma^t - 1)
  * READING (the paper does not say at which time it evaluates the energies):
@@ -476,7 +537,7 @@ void orc_diag(const int g[3], double dt, double alpha0, int nsp, const double *k
               const double *sgn, const double *m_over_me, int64_t np,
               const int32_t *species, const double *x, const double *u,
               const double *e, const double *b, double *out,
-              int nbins, double lo, double hi, int64_t *hist, int filter)
+              int nbins, double lo, double hi, int64_t *hist, int filter, int wall)
 {
     int64_t n = ncells(g);
     double *bt = (double *)malloc(sizeof(double) * 3 * n);
@@ -529,6 +590,8 @@ void orc_diag(const int g[3], double dt, double alpha0, int nsp, const double *k
                            + at(e, g, 1, i, j, k) - at(e, g, 1, i, j - 1, k)
                            + at(e, g, 2, i, j, k) - at(e, g, 2, i, j, k - 1);
                 double r = div - rho[cell_index(g, i, j, k)];
+                int idx[3] = {i, j, k};
+                if (wall >= 0 && idx[wall] == 0) r = 0.0;   /* the conductor's surface charge */
                 if (fabs(r) > rmax) rmax = fabs(r);
                 rsum += r * r;
             }

@@ -89,6 +89,11 @@ typedef struct pic_box {
     double  rho0;                             /* reference superparticles per cell, all species (eq. neandrho) */
     int64_t max_particles[PIC_MAX_SPECIES];   /* capacity per species */
     int32_t tile[3];                          /* tile edge per axis, power of two in [1, 8]; 0 = 4 */
+    int32_t walls;                            /* 0: periodic; 1 + a: perfectly conducting walls at the
+                                                 two faces normal to axis a (App. A.4: normal b and
+                                                 tangential e vanish on the wall plane, particles are
+                                                 reflected; both faces share the node plane of index 0
+                                                 along a); n[a] >= 2; not with PIC_FILTER_CURRENT */
 } pic_box;
 
 typedef struct pic_config {

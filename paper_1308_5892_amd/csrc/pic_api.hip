@@ -71,6 +71,7 @@ static void carve(Bump &A, const pic_config *cfg, std::vector<BoxHost> &bh, std:
         D.acc = A.take<double>(kAccLen);
         D.hist = A.take<int64_t>((size_t)std::max(1, cfg->hist_bins) * kMaxSpecies);
         D.alpha0 = 2.0 / (H.cfg.n_x * H.cfg.n_x * H.cfg.rho0);
+        D.wall = H.cfg.walls - 1;
         for (int s = 0; s < kMaxSpecies; ++s) {
             SpeciesDev<R> &S = D.sp[s];
             memset(&S, 0, sizeof(S));
@@ -142,6 +143,12 @@ static int validate(const pic_config *cfg, std::vector<BoxHost> &bh, std::string
                                                         : push_lds_bytes<float>(H.tile[0], H.tile[1], H.tile[2]);
         if (lds > kMaxLds) { err = "tile needs more LDS than a workgroup may use"; return PIC_EINVAL; }
         if (!(H.cfg.n_x > 0) || !(H.cfg.rho0 > 0)) { err = "n_x and rho0 must be positive"; return PIC_EINVAL; }
+        if (H.cfg.walls < 0 || H.cfg.walls > 3) { err = "walls must be 0 (periodic) or 1 + axis"; return PIC_EINVAL; }
+        if (H.cfg.walls && H.cfg.n[H.cfg.walls - 1] < 2) { err = "walls need two cells along their axis"; return PIC_EINVAL; }
+        if (H.cfg.walls && (cfg->flags & PIC_FILTER_CURRENT)) {
+            err = "current smoothing is not available with walls";
+            return PIC_EINVAL;
+        }
         H.nc = (int64_t)H.cfg.n[0] * H.cfg.n[1] * H.cfg.n[2];
         H.ntiles = 1;
         for (int a = 0; a < 3; ++a) H.ntiles *= (H.cfg.n[a] + H.tile[a] - 1) / H.tile[a];
@@ -228,6 +235,7 @@ struct pic_ctx {
     int64_t step = 0;
     size_t lds_bytes = 0;
     bool fixed444 = false;             // every tile 4x4x4: the fixed-shape push kernel
+    bool walls = false;                // some box has conducting walls
     bool pending = false;
     uint32_t flags_seen = 0;
     std::string err;
@@ -397,6 +405,8 @@ static int init_t(pic_ctx *ctx)
     }
     ctx->lds_bytes = lds;
     ctx->fixed444 = all444;
+    ctx->walls = false;
+    for (auto &H : ctx->bh) ctx->walls = ctx->walls || H.cfg.walls != 0;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     // initial segment layout: an empty repack
     return merge_t<R>(ctx, true);
@@ -535,7 +545,7 @@ static int step_t(pic_ctx *ctx, int n)
         StepConst<R> C = step_const<R>(ctx);
         mark(ctx, 0, true);
         HIPCHK(launch_push<R>(boxes, ctx->L.items_push, ctx->L.n_items, ctx->lds_bytes, C, ctx->fixed444 ? 1 : 0,
-                              ctx->stream));
+                              ctx->walls ? 1 : 0, ctx->stream));
         mark(ctx, 0, false);
         mark(ctx, 1, true);
         HIPCHK(launch_fields<R>(boxes, ctx->L.cblocks, ctx->L.n_cblocks, (R)ctx->cfg.dt, ctx->cfg.n_species, C.filter,

@@ -93,6 +93,7 @@ struct BoxDev {
     PIC_GLOBAL double *acc;        // diagnostic accumulators (kAccLen doubles)
     PIC_GLOBAL int64_t *hist;      // n_species * hist_bins
     double alpha0;                 // 2 / (n_x^2 rho0)
+    int32_t wall;                  // axis with conducting walls, -1: periodic
     SpeciesDev<R> sp[kMaxSpecies];
 };
 
@@ -172,7 +173,7 @@ struct LoadArgs {
 template <typename R> size_t push_lds_bytes(int t0, int t1, int t2);
 template <typename R>
 hipError_t launch_push(const BoxDev<R> *boxes, const Item *items, int nitems, size_t lds, const StepConst<R> &C,
-                       int fixed444, hipStream_t st);
+                       int fixed444, int walls, hipStream_t st);
 template <typename R>
 hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R dt, int nsp, int filter,
                          int clear_copy, hipStream_t st);

@@ -8,6 +8,8 @@
 // the production form (int64 fixed-point current), double the FP64 form.
 #include <hip/hip_runtime.h>
 
+#include <limits>
+
 #include "pic_internal.h"
 
 namespace pic {
@@ -477,6 +479,54 @@ __device__ inline void move_crossings(const R d[3], const R D[3], R x1[3], int d
     }
 }
 
+// Conducting wall on axis w (App. A.4): when the move d -> d + D (home-cell
+// frame; cw = home cell index along w, nw = cells along w) leaves the box
+// through a wall, the move is cut where it meets the wall: D1 takes it there,
+// P = d + D1 is that point as the deposit computes it, D2 takes the rest
+// mirrored back into the box along w, and u_w changes sign.  Returns whether
+// the move hit the wall.
+template <typename R>
+__device__ inline bool wall_hit(int w, int cw, int nw, const R d[3], const R D[3], R D1[3], R P[3], R D2[3],
+                                R u[3])
+{
+    const R xw = d[w] + D[w];
+    const bool lo = cw == 0 && xw < R(0), hi = cw == nw - 1 && xw >= R(1);
+    if (!lo && !hi) return false;
+    const R plane = hi ? R(1) : R(0);
+    const R l = (plane - d[w]) / D[w];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        D1[a] = a == w ? plane - d[w] : l * D[a];
+        asm volatile("" : "+v"(D1[a]));
+        P[a] = d[a] + D1[a];
+    }
+    R xr = R(2) * plane - xw;                    // the mirrored end along w
+    if (xr >= R(1)) xr = R(1) - R(1) / R(1 << 23);  // a move ending exactly on the upper wall
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        D2[a] = (a == w ? xr : d[a] + D[a]) - P[a];
+        asm volatile("" : "+v"(D2[a]));
+    }
+    u[w] = -u[w];
+    return true;
+}
+
+// The mirrored rest of a wall move starts at P (home-cell frame), which lies
+// in a neighbouring cell along each other axis that the first piece crossed.
+// Rebase it onto that cell: s = the cell's offset from the home cell (0 along
+// the wall axis, where P is on a face of the home cell), P in [0, 1) of it.
+template <typename R>
+__device__ inline void wall_rest_start(int w, R P[3], int s[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        s[a] = a == w ? 0 : (P[a] < R(0) ? -1 : (P[a] >= R(1) ? 1 : 0));
+        R v = P[a] - R(s[a]);
+        if (v >= R(1)) v = R(1) - R(0.5) * std::numeric_limits<R>::epsilon();   // -tiny + 1 rounded up
+        if (a != w) P[a] = v;
+    }
+}
+
 // Point where axis `ax` meets its plane (parameter l): that coordinate is the
 // plane itself, every other coordinate stays on its own side of its plane
 // (the far side once its own crossing parameter is <= l).
@@ -552,12 +602,12 @@ __device__ inline int move_bin(const TileGeom<R> &g, const TileRim &rim, const i
 template <typename R> struct PushWaves { static constexpr int value = 4; };
 template <> struct PushWaves<double> { static constexpr int value = 2; };
 
-template <typename R, int FIX>
+template <typename R, int FIX, int WALLS>
 __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const BoxDev<R> *__restrict__ boxes,
                                                       const Item *__restrict__ items, StepConst<R> C);
 
 // Overflow sweep: same physics, fields from HBM, current by global atomics.
-template <typename R>
+template <typename R, int WALLS>
 __device__ void push_overflow(const BoxDev<R> &B, int kblk, const StepConst<R> &C)
 {
     using JT = typename JType<R>::T;
@@ -592,16 +642,35 @@ __device__ void push_overflow(const BoxDev<R> &B, int kblk, const StepConst<R> &
             }
             const R ig = C.dt * fast_rsqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
             R D[3] = {ig * u[0], ig * u[1], ig * u[2]};
+            // a move through a conducting wall (App. A.4): deposit up to the
+            // wall, then the mirrored rest; the particle ends at P2 + D2
+            R D1[3], P2[3], D2[3];
+            const bool hitw = WALLS && B.wall >= 0 && valid &&
+                              wall_hit(B.wall, B.wall == 0 ? ix : (B.wall == 1 ? iy : iz), B.n[B.wall], d, D, D1, P2,
+                                       D2, u);
             if (valid) {
                 JT *J = B.J;
-                deposit_move(d, D, scale, [&](int a, int ox, int oy, int oz, R v) {
+                auto put_j = [&](int a, int ox, int oy, int oz, R v) {
                     const int i = wrap_idx(ix + ox, B.n[0]), j = wrap_idx(iy + oy, B.n[1]),
                               k = wrap_idx(iz + oz, B.n[2]);
                     atomic_add_global(&J[a * B.nc + i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)],
                                       quantize(v));
-                });
+                };
+                if (hitw) {
+                    deposit_move(d, D1, scale, put_j);
+                    R Q2[3] = {P2[0], P2[1], P2[2]};
+                    int s2[3];
+                    wall_rest_start(B.wall, Q2, s2);
+                    deposit_move(Q2, D2, scale, [&](int a, int ox, int oy, int oz, R v) {
+                        put_j(a, s2[0] + ox, s2[1] + oy, s2[2] + oz, v);
+                    });
+                } else {
+                    deposit_move(d, D, scale, put_j);
+                }
             }
             R x1[3] = {d[0] + D[0], d[1] + D[1], d[2] + D[2]}, dn[3];
+            if (hitw)
+                for (int a = 0; a < 3; ++a) x1[a] = P2[a] + D2[a];
             const int32_t nc = advance_cell(B, ix, iy, iz, x1, dn);
             store_particle(B, S, C.cur ^ 1, tile_of(B, nc), valid, nc, dn, u, id, C.flags);
         }
@@ -611,7 +680,7 @@ __device__ void push_overflow(const BoxDev<R> &B, int kblk, const StepConst<R> &
 // FP32 form: four waves per SIMD (at most 128 VGPRs), the occupancy that
 // hides the latency of the LDS gather and of the particle loads best on
 // gfx950.  FP64 form: two (its doubled registers would spill at four).
-template <typename R, int FIX>
+template <typename R, int FIX, int WALLS>
 __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const BoxDev<R> *__restrict__ boxes,
                                                       const Item *__restrict__ items, StepConst<R> C)
 {
@@ -620,7 +689,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     const Item it = items[blockIdx.x];
     const BoxDev<R> &B = boxes[it.box];
     if (it.tile < 0) {
-        push_overflow(B, -1 - it.tile, C);
+        push_overflow<R, WALLS>(B, -1 - it.tile, C);
         return;
     }
     const int T = it.tile;
@@ -821,7 +890,8 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             move_crossings(d, D, x1, dir, lam);
             const int oa = (meta >> (2 + 2 * k)) & 3, ob = (meta >> (4 + 2 * k)) & 3;   // axes of crossings k, k+1
             R ps[3], pe[3];
-            crossing_point(d, D, dir, lam, oa, sel3(oa, lam[0], lam[1], lam[2]), ps);
+            if (k == 0) { ps[0] = d[0]; ps[1] = d[1]; ps[2] = d[2]; }
+            else crossing_point(d, D, dir, lam, oa, sel3(oa, lam[0], lam[1], lam[2]), ps);
             if (k < nb) crossing_point(d, D, dir, lam, ob, sel3(ob, lam[0], lam[1], lam[2]), pe);
             else { pe[0] = x1[0]; pe[1] = x1[1]; pe[2] = x1[2]; }
             int offc[3];
@@ -909,17 +979,26 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
 #pragma unroll
             for (int a = 0; a < 3; ++a) asm volatile("" : "+v"(D[a]));
 
-            // node planes crossed by the move and their crossing parameters
-            // in increasing order (axes o0, o1, o2)
+            // node planes crossed by the move (end x1 in the home-cell frame)
             R x1[3], lam[3];
             int dir[3];
             move_crossings(d, D, x1, dir, lam);
-            const int nb = (dir[0] != 0) + (dir[1] != 0) + (dir[2] != 0);
-            int o0 = 0, o1 = 1, o2 = 2;
-            R l0 = lam[0], l1 = lam[1], l2 = lam[2];
-            if (l1 < l0) { R t = l0; l0 = l1; l1 = t; int q = o0; o0 = o1; o1 = q; }
-            if (l2 < l1) { R t = l1; l1 = l2; l2 = t; int q = o1; o1 = o2; o2 = q; }
-            if (l1 < l0) { R t = l0; l0 = l1; l1 = t; int q = o0; o0 = o1; o1 = q; }
+            // conducting walls (App. A.4): a move through a wall ends at the
+            // mirrored point P2 + D2; its deposit is the piece d -> d + D1
+            // (below) and the queued move P2 -> P2 + D2
+            bool hitw = false;
+            R P2[3], D2[3], D1[3];
+            if (WALLS && B.wall >= 0) {
+                const int w = B.wall;
+                hitw = valid && wall_hit(w, w == 0 ? ix : (w == 1 ? iy : iz), B.n[w], d, D, D1, P2, D2, u);
+                if (hitw) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        x1[a] = P2[a] + D2[a];
+                        dir[a] = x1[a] < R(0) ? -1 : (x1[a] >= R(1) ? 1 : 0);
+                    }
+                }
+            }
 
             // new cell and offset, re-binning target, and the slot claims:
             // the stayers' block of slots by one returning atomic of their
@@ -969,7 +1048,19 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             if (at >= 0) write_particle(S.buf[dst], at, ncell, dn, u, id);
 
             // deposit: the first piece (in the home cell) at once, the move
-            // into the wave's queue for its later pieces
+            // into the wave's queue for its later pieces; the crossings in
+            // increasing order of their parameter (axes o0, o1, o2)
+            if (WALLS && hitw) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) D[a] = D1[a];
+                move_crossings(d, D, x1, dir, lam);
+            }
+            const int nb = (dir[0] != 0) + (dir[1] != 0) + (dir[2] != 0);
+            int o0 = 0, o1 = 1, o2 = 2;
+            R l0 = lam[0], l1 = lam[1], l2 = lam[2];
+            if (l1 < l0) { R t = l0; l0 = l1; l1 = t; int q = o0; o0 = o1; o1 = q; }
+            if (l2 < l1) { R t = l1; l1 = l2; l2 = t; int q = o1; o1 = o2; o2 = q; }
+            if (l1 < l0) { R t = l0; l0 = l1; l1 = t; int q = o0; o0 = o1; o1 = q; }
             const int jb = (lx + 1) + __mul24(JX, ly + 1) + __mul24(JXY, lz + 1);
             R p1[3];
             if (nb == 0) {
@@ -991,6 +1082,32 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             }
             put(valid && inside && nb > 0, jb | sgnbit, 1 | (nb << 2) | (o0 << 4) | (o1 << 6) | (o2 << 8), d, D);
             while (qcount >= 64) drain();
+            if (WALLS && B.wall >= 0 && __ballot(hitw)) {
+                // the mirrored rest of the moves that hit a wall: a whole move
+                // from its first piece (next piece 0) through the queue
+                R y1[3], lb[3];
+                int db[3], s2[3];
+                wall_rest_start(B.wall, P2, s2);
+                move_crossings(P2, D2, y1, db, lb);
+                const int nb2 = (db[0] != 0) + (db[1] != 0) + (db[2] != 0);
+                int q0 = 0, q1 = 1, q2 = 2;
+                R m0 = lb[0], m1 = lb[1], m2 = lb[2];
+                if (m1 < m0) { R t = m0; m0 = m1; m1 = t; int q = q0; q0 = q1; q1 = q; }
+                if (m2 < m1) { R t = m1; m1 = m2; m2 = t; int q = q1; q1 = q2; q2 = q; }
+                if (m1 < m0) { R t = m0; m0 = m1; m1 = t; int q = q0; q0 = q1; q1 = q; }
+                const int jb2 = jb + s2[0] + __mul24(JX, s2[1]) + __mul24(JXY, s2[2]);
+                put(hitw && inside, jb2 | sgnbit, 0 | (nb2 << 2) | (q0 << 4) | (q1 << 6) | (q2 << 8), P2, D2);
+                if (hitw && !inside) {
+                    PIC_GLOBAL JT *J = B.J;
+                    deposit_move(P2, D2, scale, [&](int a, int ox, int oy, int oz, R v) {
+                        const int i = wrap_idx(ix + s2[0] + ox, B.n[0]), j = wrap_idx(iy + s2[1] + oy, B.n[1]),
+                                  k = wrap_idx(iz + s2[2] + oz, B.n[2]);
+                        atomic_add_global(&J[a * B.nc + i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)],
+                                          quantize(v));
+                    });
+                }
+                while (qcount >= 64) drain();
+            }
         }
     }
     while (qcount > 0) drain();
@@ -1086,6 +1203,8 @@ __global__ void __launch_bounds__(kBlock) advance_b_kernel(const BoxDev<R> *__re
     B.b[p] -= h * cx;
     B.b[B.nc + p] -= h * cy;
     B.b[2 * B.nc + p] -= h * cz;
+    if (B.wall >= 0 && (B.wall == 0 ? i : (B.wall == 1 ? j : k)) == 0)
+        B.b[B.wall * B.nc + p] = R(0);           // normal b on a conducting wall (App. A.4)
 }
 
 // e <- e + dt curl b + alpha0 J (App. A.3.2 and A.2, eq. max2bis); J <- 0.
@@ -1113,6 +1232,11 @@ __global__ void __launch_bounds__(kBlock) advance_e_kernel(const BoxDev<R> *__re
     B.e[p] += dt * cx + jx;
     B.e[B.nc + p] += dt * cy + jy;
     B.e[2 * B.nc + p] += dt * cz + jz;
+    if (B.wall >= 0 && (B.wall == 0 ? i : (B.wall == 1 ? j : k)) == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)              // tangential e on a conducting wall (App. A.4)
+            if (c != B.wall) B.e[c * B.nc + p] = R(0);
+    }
     J[p] = JT(0);
     J[B.nc + p] = JT(0);
     J[2 * B.nc + p] = JT(0);
@@ -1472,7 +1596,8 @@ __global__ void __launch_bounds__(kBlock) diag_fields_kernel(const BoxDev<R> *__
                            (double)fld(B.e, B, 2, i, j, k) - (double)fld(B.e, B, 2, i, j, k - 1);
         // with a smoothed current the conserved charge is the smoothed one
         const double rho = filter ? smooth27<double>(B.rho, B.n, i, j, k) / 64.0 : B.rho[p];
-        const double r = div - rho;
+        const bool on_wall = B.wall >= 0 && (B.wall == 0 ? i : (B.wall == 1 ? j : k)) == 0;
+        const double r = on_wall ? 0.0 : div - rho;   // a wall plane carries the conductor's surface charge
         v[6] = r * r;
         gmax = fabs(r);
     }
@@ -1489,26 +1614,22 @@ size_t push_lds_bytes(int t0, int t1, int t2) { return tile_lds_bytes<R>(t0, t1,
 
 template <typename R>
 hipError_t launch_push(const BoxDev<R> *boxes, const Item *items, int nitems, size_t lds, const StepConst<R> &C,
-                       int fixed444, hipStream_t st)
+                       int fixed444, int walls, hipStream_t st)
 {
     // dynamic LDS beyond 64 KiB has to be allowed per kernel, once
-    auto allow = [&](const void *k, bool &done) -> hipError_t {
-        if (lds <= 65536 || done) return hipSuccess;
-        const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e == hipSuccess) done = true;
-        return e;
+    static bool raised[4] = {false, false, false, false};
+    auto go = [&](auto kern, int v) -> hipError_t {
+        if (lds > 65536 && !raised[v]) {
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            raised[v] = true;
+        }
+        hipLaunchKernelGGL(kern, dim3(nitems), dim3(kBlock), lds, st, boxes, items, C);
+        return hipGetLastError();
     };
-    static bool raised[2] = {false, false};
-    if (fixed444) {
-        const hipError_t e = allow(reinterpret_cast<const void *>(&push_kernel<R, 1>), raised[1]);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((push_kernel<R, 1>), dim3(nitems), dim3(kBlock), lds, st, boxes, items, C);
-    } else {
-        const hipError_t e = allow(reinterpret_cast<const void *>(&push_kernel<R, 0>), raised[0]);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((push_kernel<R, 0>), dim3(nitems), dim3(kBlock), lds, st, boxes, items, C);
-    }
-    return hipGetLastError();
+    if (walls) return fixed444 ? go(push_kernel<R, 1, 1>, 3) : go(push_kernel<R, 0, 1>, 2);
+    return fixed444 ? go(push_kernel<R, 1, 0>, 1) : go(push_kernel<R, 0, 0>, 0);
 }
 
 template <typename R>
@@ -1710,7 +1831,7 @@ hipError_t launch_spectrum(const BoxDev<R> *boxes, int box, const int n[3], int 
 #define PIC_INSTANTIATE(R)                                                                                     \
     template size_t push_lds_bytes<R>(int, int, int);                                                         \
     template hipError_t launch_push<R>(const BoxDev<R> *, const Item *, int, size_t, const StepConst<R> &,   \
-                                       int, hipStream_t);                                                     \
+                                       int, int, hipStream_t);                                                \
     template hipError_t launch_fields<R>(const BoxDev<R> *, const CellBlock *, int, R, int, int, int,          \
                                          hipStream_t);                                                        \
     template hipError_t launch_advance_b<R>(const BoxDev<R> *, const CellBlock *, int, R, hipStream_t);       \

@@ -35,7 +35,7 @@ class pic_species(C.Structure):
 
 class pic_box(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("n_x", C.c_double), ("rho0", C.c_double),
-                ("max_particles", C.c_int64 * MAX_SPECIES), ("tile", C.c_int32 * 3)]
+                ("max_particles", C.c_int64 * MAX_SPECIES), ("tile", C.c_int32 * 3), ("walls", C.c_int32)]
 
 
 class pic_config(C.Structure):
@@ -151,6 +151,7 @@ def make_config(boxes, species, dt, sort_interval=0, fp64=False, track_ids=False
         mp = list(b["max_particles"]) + [0] * (MAX_SPECIES - len(b["max_particles"]))
         arr[i].max_particles[:] = [int(v) for v in mp]
         arr[i].tile[:] = list(b.get("tile", (4, 4, 4)))
+        arr[i].walls = int(b.get("walls", 0))
     cfg = pic_config()
     cfg.n_boxes = len(boxes)
     cfg.boxes = C.cast(arr, C.POINTER(pic_box))
@@ -308,6 +309,7 @@ def autotune(boxes, species, dt, loads, steps=10, **kw):
     for i, b in enumerate(boxes):
         t = dict(b)
         t["tile"] = tuple(arr[i].tile[:])
+        t["walls"] = arr[i].walls
         tuned.append(t)
     return tuned, out.sort_interval, {"ms_per_step": res.ms_per_step, "ms_per_step_default": res.ms_per_step_default,
                                       "trials": res.trials}

@@ -460,3 +460,138 @@ def test_filamentation_growth_rates_in_the_papers_range():
     r_fast = growth_time(pk) / tau_max - 1.0
     f_lo, f_hi = min(ref["fast_mode_excess"].values()), max(ref["fast_mode_excess"].values())
     assert f_lo - 0.5 * (f_hi - f_lo) - 0.05 <= r_fast <= f_hi + 0.5 * (f_hi - f_lo) + 0.05, r_fast
+
+
+# ------------------------------------------------ conducting walls (App. A.4)
+
+def _wall_sim(dims, n_x, rho0, maxp, fp64, species=G.PAIR, wall_axis=0):
+    from paper_1308_5892_amd import pic as P
+    boxes = [{"n": tuple(dims), "n_x": n_x, "rho0": rho0, "max_particles": list(maxp), "walls": 1 + wall_axis}]
+    return P.Simulation(boxes, species, 0.5, fp64=fp64, track_ids=True)
+
+
+@pytest.mark.parametrize("fp64,tol", [(False, 2e-5), (True, 1e-12)])
+def test_standing_wave_between_walls(fp64, tol):
+    # an odd standing mode between walls at x = 0 and x = N, against the oracle
+    # with the same walls (its own closed-form pin is in the oracle tests)
+    dims, m, dt = (16, 4, 4), 3, 0.5
+    n = int(np.prod(dims))
+    k = np.pi * m / dims[0]
+    om = 2 * np.arcsin(dt * np.sin(k / 2)) / dt
+    amp = -dt * np.sin(k / 2) / np.sin(om * dt / 2)
+    i = np.arange(n) % dims[0]
+    e = np.zeros(3 * n)
+    b = np.zeros(3 * n)
+    e[n:2 * n] = np.sin(k * i)
+    b[2 * n:] = amp * np.cos(k * (i + 0.5)) * np.sin(-om * dt / 2)
+    s = _wall_sim(dims, 10.0, 2.0, [1, 1], fp64)
+    st = G.oracle_state(dims, 10.0, 2.0)
+    st.wall = 0
+    G.start(s, st, [], e=e, b=b, fp64=fp64)
+    s.step(40)
+    st.step(40)
+    e1, b1, _ = s.fields(0)
+    assert np.abs(e1 - st.e).max() < tol
+    assert np.abs(b1 - st.b).max() < tol
+    assert np.abs(st.e[n:2 * n] - np.sin(k * i) * np.cos(om * 40 * dt)).max() < 1e-6
+    s.close()
+
+
+@pytest.mark.parametrize("fp64,tol", [(False, 1e-5), (True, 1e-11)])
+def test_hot_plasma_bouncing_between_walls(fp64, tol):
+    rng = np.random.default_rng(31)
+    dims, ppc = (12, 8, 8), 4
+    npairs = ppc * int(np.prod(dims))
+    s = _wall_sim(dims, 10.0, 2 * ppc, [npairs, npairs], fp64)
+    st = G.oracle_state(dims, 10.0, 2 * ppc)
+    st.wall = 0
+    x = rng.uniform(0, 1, (npairs, 3)) * np.array(dims)
+    x[: npairs // 8, 0] = rng.choice([0.01, dims[0] - 0.01], npairs // 8)    # start at the walls
+    u = 0.8 * rng.standard_normal((npairs, 3))
+    G.start(s, st, [(x, u), (x, -u)], fp64=fp64)
+    s.step(10)
+    st.step(10)
+    for sp in range(2):
+        xg, ug, _ = s.particles(0, sp)
+        assert G.u_rel_err(ug, st.u[st.species == sp], 1e-2).max() < tol
+        assert np.abs(G.wrap_delta(xg, st.x[st.species == sp], dims)).max() < 100 * tol
+        assert np.all((xg[:, 0] >= 0) & (xg[:, 0] < dims[0]))
+    e1, b1, _ = s.fields(0)
+    assert np.abs(e1 - st.e).max() < (1e-11 if fp64 else 1e-4) * np.abs(st.e).max()
+    d = s.diag(0)
+    assert d["flags"] == 0
+    assert d["gauss_max"] < (1e-13 if fp64 else 1e-4 * 2.0 / (100 * 2 * ppc) * ppc), d["gauss_max"]
+    s.close()
+
+
+@pytest.mark.parametrize("fp64,tol", [(False, 1e-5), (True, 1e-11)])
+def test_single_harris_sheet_between_walls(fp64, tol):
+    # the paper's tearing set-up (Sect. 3.4, App. C): one pair-plasma Harris
+    # sheet in the middle of the box, reflecting walls in x, no background
+    from oracle import oracle as O
+    dims, ppc, n_x = (32, 16, 4), 4, 4.0
+    hp = O.harris_params(1.0, 0.68, 1.0, 1.0)
+    L, b0 = hp["L_over_de"] * n_x, hp["wce_over_wpe"] / n_x
+    c = dims[0] / 2.0
+    npairs = int(round(ppc * (np.prod(dims) / dims[0]) * 2 * L * np.tanh(c / L)))
+    A = {"theta": 1.0, "gb": -0.68, "axis": 2}
+    B = {"theta": 1.0, "gb": 0.68, "axis": 2}
+    n = int(np.prod(dims))
+    i = np.arange(n) % dims[0]
+    b = np.zeros(3 * n)
+    b[n:2 * n] = b0 * np.tanh((i + 0.5 - c) / L)
+    s = _wall_sim(dims, n_x, 2 * ppc, [npairs + 16] * 2, fp64)
+    s.harris_field(0, 0, 1, b0, L, [c])
+    s.load(0, 0, 1, (1.0, -0.68, 2), (1.0, 0.68, 2), ppc, seed=7, profile=1, profile_axis=0, centre=c, thickness=L,
+           half_width=c)
+    parts = G.oracle_loaded(dims, 0.5, n_x, 2 * ppc, G.PAIR,
+                            [dict(seed=7, stream=0, npairs=npairs, A=A, B=B,
+                                  prof=dict(profile=1, paxis=0, centre=c, L=L, halfw=c))], b=b)
+    for sp in range(2):
+        x, u, _ = s.particles(0, sp)
+        assert len(x) == npairs
+        assert G.u_rel_err(u, parts[sp][1], 1e-3).max() < (1e-9 if fp64 else 2e-6)
+    st = G.oracle_state(dims, n_x, 2 * ppc)
+    st.wall = 0
+    G.start(s, st, parts, b=b, fp64=fp64)
+    s.step(10)
+    st.step(10)
+    for sp in range(2):
+        _, u, _ = s.particles(0, sp)
+        assert G.u_rel_err(u, st.u[st.species == sp], 1e-2).max() < tol
+    _, b1, _ = s.fields(0)
+    assert np.abs(b1 - st.b).max() < (1e-12 if fp64 else 1e-5) * np.abs(st.b).max()
+    assert s.diag(0)["flags"] == 0
+    s.close()
+
+
+# single moves through a wall, some crossing other cell planes before or
+# after the wall: the current of each against the oracle's after one step
+_WALL_MOVES = [
+    ((11.95, 3.5, 3.5), (2.0, 0.3, -0.2)),
+    ((11.95, 3.95, 3.5), (2.0, 2.0, 0.0)),       # crosses y before the wall
+    ((11.9, 3.97, 3.05), (2.0, 0.4, -2.0)),      # crosses z before the wall, y after it
+    ((0.05, 3.02, 3.5), (-2.0, -2.0, 0.4)),      # crosses y before the wall
+    ((0.05, 3.5, 3.97), (-2.0, 0.2, 2.5)),       # crosses z before the wall
+    ((11.99, 0.01, 7.99), (1.0, -1.0, 1.0)),     # at a box corner
+    ((0.0, 3.5, 3.5), (-1.0, 0.0, 0.0)),         # starts on the wall
+]
+
+
+@pytest.mark.parametrize("fp64,tol", [(False, 2e-9), (True, 1e-16)])
+@pytest.mark.parametrize("move", _WALL_MOVES)
+def test_single_moves_through_a_wall(fp64, tol, move):
+    x, u = move
+    dims = (12, 8, 8)
+    s = _wall_sim(dims, 10.0, 2.0, [4, 4], fp64)
+    st = G.oracle_state(dims, 10.0, 2.0)
+    st.wall = 0
+    G.start(s, st, [(np.array([x]), np.array([u])), (np.zeros((0, 3)), np.zeros((0, 3)))], fp64=fp64)
+    s.step(1)
+    st.step(1)
+    e1, _, _ = s.fields(0)
+    assert np.abs(e1 - st.e).max() < tol
+    xg, ug, _ = s.particles(0, 0)
+    assert np.abs(G.wrap_delta(xg, st.x, dims)).max() < 1e-6
+    assert np.abs(ug - st.u).max() == 0.0
+    s.close()

@@ -497,16 +497,20 @@ def test_standing_wave_between_walls(fp64, tol):
     s.close()
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
 @pytest.mark.parametrize("fp64,tol", [(False, 1e-5), (True, 1e-11)])
-def test_hot_plasma_bouncing_between_walls(fp64, tol):
-    rng = np.random.default_rng(31)
-    dims, ppc = (12, 8, 8), 4
+def test_hot_plasma_bouncing_between_walls(fp64, tol, axis):
+    # walls on each axis in turn; the wall axis is the longest, and ragged
+    # against the 4^3 tiles along the other two
+    rng = np.random.default_rng(31 + axis)
+    dims = {0: (12, 10, 9), 1: (10, 12, 9), 2: (10, 9, 12)}[axis]
+    ppc = 4
     npairs = ppc * int(np.prod(dims))
-    s = _wall_sim(dims, 10.0, 2 * ppc, [npairs, npairs], fp64)
+    s = _wall_sim(dims, 10.0, 2 * ppc, [npairs, npairs], fp64, wall_axis=axis)
     st = G.oracle_state(dims, 10.0, 2 * ppc)
-    st.wall = 0
+    st.wall = axis
     x = rng.uniform(0, 1, (npairs, 3)) * np.array(dims)
-    x[: npairs // 8, 0] = rng.choice([0.01, dims[0] - 0.01], npairs // 8)    # start at the walls
+    x[: npairs // 8, axis] = rng.choice([0.01, dims[axis] - 0.01], npairs // 8)    # start at the walls
     u = 0.8 * rng.standard_normal((npairs, 3))
     G.start(s, st, [(x, u), (x, -u)], fp64=fp64)
     s.step(10)
@@ -515,7 +519,7 @@ def test_hot_plasma_bouncing_between_walls(fp64, tol):
         xg, ug, _ = s.particles(0, sp)
         assert G.u_rel_err(ug, st.u[st.species == sp], 1e-2).max() < tol
         assert np.abs(G.wrap_delta(xg, st.x[st.species == sp], dims)).max() < 100 * tol
-        assert np.all((xg[:, 0] >= 0) & (xg[:, 0] < dims[0]))
+        assert np.all((xg[:, axis] >= 0) & (xg[:, axis] < dims[axis]))
     e1, b1, _ = s.fields(0)
     assert np.abs(e1 - st.e).max() < (1e-11 if fp64 else 1e-4) * np.abs(st.e).max()
     d = s.diag(0)

@@ -4,6 +4,7 @@ fails without the wall condition for an odd mode), particles bounce off the
 walls in straight lines, and Gauss's law holds in the interior of a thermal
 plasma bouncing between walls."""
 import numpy as np
+import pytest
 
 
 def _standing_wave(n, m, dt, steps):
@@ -34,14 +35,20 @@ def test_standing_wave_between_walls(orc):
             assert err > 1e-2        # an odd mode is not periodic: the wall condition is what holds it
 
 
-def test_particles_bounce_off_the_walls(orc):
+@pytest.mark.parametrize("w", [0, 1, 2])
+def test_particles_bounce_off_the_walls(orc, w):
     # a co-located electron-positron pair deposits no net current, so the fields
     # stay zero and both move in straight lines between bounces
-    dims, dt = (6, 4, 4), 0.5
-    st = orc.State(dims, dt, 10.0, 2.0, [(-1.0, 1.0), (1.0, 1.0)])
-    st.wall = 0
-    x0 = np.array([[0.3, 1.5, 2.5], [5.6, 0.5, 3.9]])
-    u0 = np.array([[-0.9, 0.2, 0.0], [0.7, -0.3, 0.4]])
+    dt = 0.5
+    dims = [4, 4, 4]
+    dims[w] = 6
+    st = orc.State(tuple(dims), dt, 10.0, 2.0, [(-1.0, 1.0), (1.0, 1.0)])
+    st.wall = w
+    perm = [(w + k) % 3 for k in range(3)]          # the wall axis takes the role of x
+    x0 = np.zeros((2, 3))
+    u0 = np.zeros((2, 3))
+    x0[:, perm] = [[0.3, 1.5, 2.5], [5.6, 0.5, 3.9]]
+    u0[:, perm] = [[-0.9, 0.2, 0.0], [0.7, -0.3, 0.4]]
     st.add_particles(0, x0, u0)
     st.add_particles(1, x0, u0)
     steps = 23
@@ -49,24 +56,27 @@ def test_particles_bounce_off_the_walls(orc):
     for p in range(2):
         v = u0[p] / np.sqrt(1 + u0[p] @ u0[p])
         x = x0[p] + steps * dt * v
-        L = dims[0]
-        # unfold the bounces along x: reflect into [0, L)
-        xx = np.mod(x[0], 2 * L)
-        xr = xx if xx < L else 2 * L - xx
+        L = dims[w]
+        # unfold the bounces along the wall axis: reflect into [0, L)
+        xx = np.mod(x[w], 2 * L)
+        want_x = np.mod(x, dims)
+        want_x[w] = xx if xx < L else 2 * L - xx
         sgn = 1.0 if xx < L else -1.0
-        want_x = np.array([xr, np.mod(x[1], dims[1]), np.mod(x[2], dims[2])])
         for s in range(2):
             got = st.x[st.species == s][p]
             assert np.abs(got - want_x).max() < 1e-12, (got, want_x)
-            assert abs(st.u[st.species == s][p][0] - sgn * u0[p][0]) < 1e-14
+            assert abs(st.u[st.species == s][p][w] - sgn * u0[p][w]) < 1e-14
     assert np.abs(st.e).max() < 1e-15 and np.abs(st.b).max() < 1e-15
 
 
-def test_gauss_law_in_the_interior_with_walls(orc):
-    dims, ppc = (8, 6, 6), 6
-    rng = np.random.default_rng(4)
-    st = orc.State(dims, 0.5, 10.0, 2 * ppc, [(-1.0, 1.0), (1.0, 1.0)])
-    st.wall = 0
+@pytest.mark.parametrize("w", [0, 1, 2])
+def test_gauss_law_in_the_interior_with_walls(orc, w):
+    dims = [6, 6, 6]
+    dims[w] = 8
+    ppc = 6
+    rng = np.random.default_rng(4 + w)
+    st = orc.State(tuple(dims), 0.5, 10.0, 2 * ppc, [(-1.0, 1.0), (1.0, 1.0)])
+    st.wall = w
     npairs = ppc * int(np.prod(dims))
     x = rng.uniform(0, 1, (npairs, 3)) * np.array(dims)
     st.add_particles(0, x, 0.5 * rng.standard_normal((npairs, 3)))
@@ -75,8 +85,12 @@ def test_gauss_law_in_the_interior_with_walls(orc):
     d = st.diag()
     assert d["gauss_max"] < 1e-12, d["gauss_max"]
     assert int(d["count"].sum()) == 2 * npairs
-    assert np.all((st.x[:, 0] >= 0) & (st.x[:, 0] < dims[0]))
+    assert np.all((st.x[:, w] >= 0) & (st.x[:, w] < dims[w]))
     # the walls keep tangential e and normal b at zero on their plane
     n = int(np.prod(dims))
-    wallp = (np.arange(n) % dims[0]) == 0
-    assert np.all(st.e[n:2 * n][wallp] == 0) and np.all(st.e[2 * n:][wallp] == 0) and np.all(st.b[:n][wallp] == 0)
+    idx = np.arange(n)
+    coord = [idx % dims[0], (idx // dims[0]) % dims[1], idx // (dims[0] * dims[1])]
+    wallp = coord[w] == 0
+    for c in range(3):
+        f = st.b if c == w else st.e
+        assert np.all(f[c * n:(c + 1) * n][wallp] == 0)

@@ -1517,27 +1517,71 @@ __device__ inline void block_sum_to(double *dst, double v)
 
 // Per-particle diagnostics of one box (items of that box only): gamma^t from
 // u^- = u^{t-dt/2} + (k dt/2) E(x^t) (READING: the mover's own gamma^t), the
-// k = 0 momentum, the gamma-1 histogram and the CIC charge density.
+// k = 0 momentum, the gamma-1 histogram and the CIC charge density.  A tile
+// item stages the node-averaged e of its (t+1)^3 nodes in LDS once and sums its
+// charge and histogram there (one global atomic per node and bin); the
+// overflow items gather from HBM and add to the global sums directly.
+constexpr int kDiagNodes = 9 * 9 * 9;   // nodes of the largest tile (8^3 cells)
+constexpr int kDiagHist = 512;          // histograms up to this many bins are summed in LDS
 template <typename R>
 __global__ void __launch_bounds__(kBlock) diag_particles_kernel(const BoxDev<R> *__restrict__ boxes,
                                                                 const Item *__restrict__ items, StepConst<R> C)
 {
+    __shared__ R sE[3 * kDiagNodes];
+    __shared__ double srho[kDiagNodes];
+    __shared__ unsigned shist[kDiagHist];
     const Item it = items[blockIdx.x];
     const BoxDev<R> &B = boxes[it.box];
     const R hdt = R(0.5) * C.dt;
+    const int tid = threadIdx.x;
+    const bool in_tile = it.tile >= 0;
+    TileGeom<R> g{};
+    if (in_tile) {
+        g = tile_geom<R>(B, it.tile);
+        // node-averaged e (App. A.3.3): the same values the HBM gather forms
+        for (int q = tid; q < g.NN; q += kBlock) {
+            const int i = g.o[0] + q % g.NX, j = g.o[1] + (q / g.NX) % g.NY, k = g.o[2] + q / (g.NX * g.NY);
+            sE[q] = R(0.5) * (fld(B.e, B, 0, i - 1, j, k) + fld(B.e, B, 0, i, j, k));
+            sE[g.NN + q] = R(0.5) * (fld(B.e, B, 1, i, j - 1, k) + fld(B.e, B, 1, i, j, k));
+            sE[2 * g.NN + q] = R(0.5) * (fld(B.e, B, 2, i, j, k - 1) + fld(B.e, B, 2, i, j, k));
+            srho[q] = 0.0;
+        }
+    }
+    const bool lhist = C.hist_bins > 0 && C.hist_bins <= kDiagHist;
     for (int s = 0; s < C.nsp; ++s) {
         const SpeciesDev<R> &S = B.sp[s];
         int first, stride;
         const TileRanges r = item_range(B, S, C.cur, it.tile, first, stride);
         const PBuf<R> &P = S.buf[C.cur];
+        if (lhist)
+            for (int q = tid; q < C.hist_bins; q += kBlock) shist[q] = 0u;
+        __syncthreads();
+        const double q = (double)C.qs[s] * B.alpha0;
         double acc[6] = {0, 0, 0, 0, 0, 0};
         for (int p = first; p < r.n; p += stride) {
             const int idx = r.slot(p);
             const int32_t cell = P.cell[idx];
             const int ix = cell_x(cell), iy = cell_y(cell), iz = cell_z(cell);
             R d[3] = {P.d[0][idx], P.d[1][idx], P.d[2][idx]};
-            R E[3], Bf[3];
-            gather_global(B, ix, iy, iz, d, hdt, E, Bf);
+            R E[3];
+            int nb = 0;
+            if (in_tile) {
+                nb = (ix - g.o[0]) + g.NX * ((iy - g.o[1]) + g.NY * (iz - g.o[2]));
+                E[0] = E[1] = E[2] = R(0);
+                for (int kk = 0; kk < 2; ++kk)
+                    for (int jj = 0; jj < 2; ++jj)
+                        for (int ii = 0; ii < 2; ++ii) {
+                            const R w = (ii ? d[0] : R(1) - d[0]) * (jj ? d[1] : R(1) - d[1]) *
+                                        (kk ? d[2] : R(1) - d[2]);
+                            const int n = nb + ii + g.NX * (jj + g.NY * kk);
+                            E[0] += w * sE[n];
+                            E[1] += w * sE[g.NN + n];
+                            E[2] += w * sE[2 * g.NN + n];
+                        }
+            } else {
+                R Bf[3];
+                gather_global(B, ix, iy, iz, d, hdt, E, Bf);
+            }
             double um[3];
             for (int a = 0; a < 3; ++a)
                 um[a] = (double)P.u[a][idx] + 0.5 * (double)C.kq[s] * (double)C.dt * (double)E[a];
@@ -1550,21 +1594,41 @@ __global__ void __launch_bounds__(kBlock) diag_particles_kernel(const BoxDev<R> 
                 const double v = log10(gm1 > 1e-300 ? gm1 : 1e-300);
                 int bin = (int)floor((v - C.hist_lo) / (C.hist_hi - C.hist_lo) * C.hist_bins);
                 bin = bin < 0 ? 0 : (bin >= C.hist_bins ? C.hist_bins - 1 : bin);
-                atomicAdd(reinterpret_cast<unsigned long long *>(&B.hist[s * C.hist_bins + bin]), 1ull);
+                if (lhist) atomicAdd(&shist[bin], 1u);
+                else atomicAdd(reinterpret_cast<unsigned long long *>(&B.hist[s * C.hist_bins + bin]), 1ull);
             }
-            const double q = (double)C.qs[s] * B.alpha0;
             for (int kk = 0; kk < 2; ++kk)
                 for (int jj = 0; jj < 2; ++jj)
                     for (int ii = 0; ii < 2; ++ii) {
                         const double w = (ii ? (double)d[0] : 1.0 - (double)d[0]) *
                                          (jj ? (double)d[1] : 1.0 - (double)d[1]) *
                                          (kk ? (double)d[2] : 1.0 - (double)d[2]);
-                        const int i = wrap_idx(ix + ii, B.n[0]), j = wrap_idx(iy + jj, B.n[1]),
-                                  k = wrap_idx(iz + kk, B.n[2]);
-                        atomicAdd(&B.rho[i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)], q * w);
+                        if (in_tile) {
+                            atomicAdd(&srho[nb + ii + g.NX * (jj + g.NY * kk)], q * w);
+                        } else {
+                            const int i = wrap_idx(ix + ii, B.n[0]), j = wrap_idx(iy + jj, B.n[1]),
+                                      k = wrap_idx(iz + kk, B.n[2]);
+                            atomicAdd(&B.rho[i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)], q * w);
+                        }
                     }
         }
-        for (int q = 0; q < 6; ++q) block_sum_to<R>(&B.acc[kAccSp + 6 * s + q], acc[q]);
+        for (int k = 0; k < 6; ++k) block_sum_to<R>(&B.acc[kAccSp + 6 * s + k], acc[k]);
+        if (lhist) {
+            __syncthreads();
+            for (int b = tid; b < C.hist_bins; b += kBlock)
+                if (shist[b]) atomicAdd(reinterpret_cast<unsigned long long *>(&B.hist[s * C.hist_bins + b]),
+                                        (unsigned long long)shist[b]);
+            __syncthreads();
+        }
+    }
+    if (in_tile) {
+        __syncthreads();
+        for (int q = tid; q < g.NN; q += kBlock)
+            if (srho[q] != 0.0) {
+                const int i = wrap_idx(g.o[0] + q % g.NX, B.n[0]), j = wrap_idx(g.o[1] + (q / g.NX) % g.NY, B.n[1]),
+                          k = wrap_idx(g.o[2] + q / (g.NX * g.NY), B.n[2]);
+                atomicAdd(&B.rho[i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)], srho[q]);
+            }
     }
 }
 

@@ -52,6 +52,73 @@ def test_energy_drift_fp32_tracks_fp64_over_1000_steps():
     assert np.abs(curves[True]).max() < 2e-2, curves[True]
 
 
+def _k0_peak(series, dt_sample, omin):
+    """Frequency of the largest peak of the time-Fourier power of a sampled
+    series (Sect. 3.1: F(omega) of the k = 0 momentum), Hann window, 16x
+    zero padding."""
+    x = np.asarray(series, dtype=float)
+    x = x - x.mean()
+    pad = 16 * len(x)
+    F = np.abs(np.fft.rfft(x * np.hanning(len(x)), pad)) ** 2
+    om = 2 * np.pi * np.fft.rfftfreq(pad, d=dt_sample)
+    return om[np.argmax(F * (om > omin))]
+
+
+def test_thermal64_long_run_statistics_fp32_vs_fp64():
+    # The benchmark state at full size (64^3 cells, 64 pairs/cell, theta =
+    # 0.1, n_x = 10, dt = 0.5), loaded by the device loader with the same seed
+    # in both forms and run for 2000 steps (16 plasma periods) with the
+    # diagnostics every 5 steps.  Statistics, not trajectories:
+    # * total-energy drift: the FP32 / fixed-point curve stays within 1e-3 of
+    #   the FP64 form's (measured: 1e-7); the drift itself (the scheme's
+    #   self-heating, Sect. 3.1.3) is below 1 % per 1000 steps;
+    # * the field-fluctuation level (time-averaged field energy over the
+    #   second half) agrees to 1 %;
+    # * the k = 0 momentum spectrum F(omega) (Sect. 3.1) of each axis peaks at
+    #   the same frequency in both forms, and at the plasma pulsation: for a
+    #   pair plasma omega_P^2 = 2 omega_pe^2, each species' response reduced
+    #   by the Maxwell-Juttner average <(1 - beta^2/3)/gamma> at theta = 0.1,
+    #   and shifted by the leapfrog's sin(omega dt/2) = omega_P dt/2.
+    from scipy import integrate
+    dims, ppc, n_x, dt, theta = (64, 64, 64), 64, 10.0, 0.5, 0.1
+    npairs = ppc * int(np.prod(dims))
+    every, nsteps = 5, 2000
+    runs = {}
+    for fp64 in (False, True):
+        s = G.sim(dims, n_x, 2.0 * ppc, [npairs, npairs], dt=dt, fp64=fp64, sort_interval=50)
+        s.load(0, 0, 1, (theta, 0.0, 1), (theta, 0.0, 1), ppc, seed=2)
+        rows = []
+        for k in range(0, nsteps + 1, every):
+            if k:
+                s.step(every)
+            d = s.diag(0)
+            rows.append([_energy(d), d["W_E"].sum() + d["W_B"].sum()] + list(d["P"][0]))
+        d = s.diag(0)
+        assert d["flags"] == 0 and d["count"].tolist() == [npairs, npairs]
+        assert d["gauss_max"] < (1e-13 if fp64 else 1e-7), d["gauss_max"]
+        s.close()
+        runs[fp64] = np.array(rows)
+    drift = {f: r[:, 0] / r[0, 0] - 1.0 for f, r in runs.items()}
+    half = nsteps // every // 2
+    assert np.abs(drift[False] - drift[True])[: half + 1].max() < 1e-3
+    assert np.abs(drift[False] - drift[True]).max() < 1e-3
+    assert 0 < drift[True][half] < 1e-2, drift[True][half]
+    wf = {f: r[half:, 1].mean() for f, r in runs.items()}
+    assert abs(wf[False] / wf[True] - 1.0) < 1e-2, wf
+
+    def mj(g):
+        w = lambda p: p * p * np.exp(-(np.sqrt(1 + p * p) - 1) / theta)
+        return integrate.quad(lambda p: g(p) * w(p), 0, 60)[0] / integrate.quad(w, 0, 60)[0]
+    red = mj(lambda p: (1 - p * p / (1 + p * p) / 3) / np.sqrt(1 + p * p))
+    om_p = np.sqrt(2.0 * red) / n_x
+    om_theory = 2 / dt * np.arcsin(om_p * dt / 2)
+    bin_w = 2 * np.pi / (nsteps * dt)
+    for a in range(3):
+        pk = {f: _k0_peak(r[:, 2 + a], every * dt, 0.2 * om_theory) for f, r in runs.items()}
+        assert abs(pk[False] - pk[True]) < bin_w, pk
+        assert abs(pk[True] / om_theory - 1.0) < 0.02, (a, pk, om_theory)
+
+
 def test_energy_curve_fp64_form_follows_oracle_100_steps():
     w = W.THERMAL16
     dims, ppc = w["dims"], w["ppc"]

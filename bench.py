@@ -80,9 +80,14 @@ def harris_parameters(w):
             "gu_i": (2.0 * w["chi"] - 1.0) * w["gu_e"]}
 
 
-def workload(name, tile):
+# box classes of the ensemble breakdown, by pairs per cell per species
+ENSEMBLE_CLASSES = (("ppc 4-15", 4, 16), ("ppc 16-63", 16, 64), ("ppc 64-256", 64, 257))
+
+
+def workload(name, tile, ppc_range=None):
     """Boxes, species, dt, loads (pic_load_desc list) and Harris fields of one
-    workload family, with every box on the given tile shape."""
+    workload family, with every box on the given tile shape.  For the ensemble,
+    ppc_range = (lo, hi) keeps only the boxes with lo <= ppc < hi."""
     from paper_1308_5892_amd import pic as P
     import pic_inputs as W
     pair = [(-1.0, 1.0), (1.0, 1.0)]
@@ -126,6 +131,8 @@ def workload(name, tile):
     elif name == "ensemble":
         spec = W.ENSEMBLE
         blist = W.ensemble_boxes(spec)
+        if ppc_range is not None:
+            blist = [bx for bx in blist if ppc_range[0] <= bx["ppc"] < ppc_range[1]]
         boxes = []
         for bx in blist:
             n = bx["dims"][0] * bx["dims"][1] * bx["dims"][2] * bx["ppc"]
@@ -136,7 +143,8 @@ def workload(name, tile):
                  for i, bx in enumerate(blist)]
     else:
         raise SystemExit(f"unknown workload {name}")
-    return {"boxes": boxes, "species": species, "dt": dt, "loads": loads, "harris": harris}
+    return {"boxes": boxes, "species": species, "dt": dt, "loads": loads, "harris": harris,
+            "thetas": [bx["theta"] for bx in blist] if name == "ensemble" else None}
 
 
 def make_sim(wl, fp64, sort_interval):
@@ -237,6 +245,8 @@ def main():
                     help="smooth the current with the 27-point filter before it enters e")
     ap.add_argument("--autotune", action="store_true",
                     help="pick tile shapes and sort interval with pic_autotune before timing")
+    ap.add_argument("--no-breakdown", action="store_true",
+                    help="ensemble: skip timing each box class (by pairs per cell) in its own launch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run a plain copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -299,6 +309,26 @@ def main():
         cpu = cpu_baseline(W.THERMAL64)
         log(f"CPU: {cpu['value'] / 1e6:.2f} M pushes/s")
 
+    classes = None
+    if wl == "ensemble" and not args.no_breakdown:
+        # per-class throughput: each class of boxes in its own launch, same
+        # tiles and sort interval, half the timed steps
+        classes = []
+        for label, lo, hi in ENSEMBLE_CLASSES:
+            sub = workload(wl, tuple(args.tile), (lo, hi))
+            if tune is not None:
+                sub["boxes"] = [dict(b, tile=tuple(tune["tiles"][0])) for b in sub["boxes"]]
+            rc = time_form(sub, False, max(1, args.steps // 2), args.warmup, sort_interval)
+            pc = rc["timing"]["push_ms"] / max(1, rc["timing"]["push_launches"]) / 1e3
+            bc = 56.0 * rc["npart"] + 48.0 * rc["cells"]
+            classes.append({"class": label, "boxes": len(sub["boxes"]), "particles": rc["npart"],
+                            "cells": rc["cells"], "mean_theta": sum(sub["thetas"]) / len(sub["thetas"]),
+                            "pushes_per_s": rc["npart"] * max(1, args.steps // 2) / rc["seconds"],
+                            "push_kernel_ms": pc * 1e3, "roofline_frac": bc / pc / 1e9 / HBM_PEAK_GBS,
+                            "flags": rc["diag"]["flags"]})
+            log(f"class {label}: {len(sub['boxes'])} boxes, {rc['npart']} particles, "
+                f"{classes[-1]['pushes_per_s'] / 1e9:.2f} G pushes/s, roofline {classes[-1]['roofline_frac']:.3f}")
+
     d = r32["diag"]
     out = {
         "metric": METRIC, "value": value, "unit": "pushes/s", "n_gpus": 1, "steps": args.steps,
@@ -316,6 +346,7 @@ def main():
                      "whole_step_frac": value * step_bytes / npart / 1e9 / HBM_PEAK_GBS},
         "cpu_baseline": cpu,
         "fp64_form": fp64,
+        "classes": classes,
         "check": {"flags": d["flags"], "particles": d["count"], "gauss_max": d["gauss_max"],
                   "overflow": d["n_overflow"]},
     }

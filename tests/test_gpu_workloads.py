@@ -417,6 +417,41 @@ def test_full_size_harris_512x256x4():
     s.close()
 
 
+@pytest.mark.slow
+def test_double_harris_holds_its_equilibrium_500_steps():
+    # The Harris workload at full size through the device loader and sheet
+    # field (App. C relations), then the benchmark's timing window of 500
+    # steps: the sheet's b energy stays within 1e-3 of its start and the
+    # plane-averaged b profile across the sheets within 1 % of the peak field
+    # (measured: 4e-5 and 0.2 %); no particle is lost.
+    w = dict(W.HARRIS)
+    dims = w["dims"]
+    species, _, loads, gpu_loads, hf = G.harris_setup(w)
+    from paper_1308_5892_amd import pic as P
+    hp_b0 = hf[2]
+    cap = sum(ld["npairs"] for ld in loads) + 1024
+    s = P.Simulation([{"n": dims, "n_x": w["n_x"], "rho0": w["rho0"], "max_particles": [cap, cap], "tile": (4, 4, 4)}],
+                     species, w["dt"], sort_interval=50)
+    s.harris_field(0, *hf)
+    for A, B, ppc, kw in gpu_loads:
+        s.load(0, 0, 1, A, B, ppc, **kw)
+    s.step(0)
+    n = int(np.prod(dims))
+
+    def by_profile():
+        _, b, _ = s.fields(0)
+        return b[n:2 * n].reshape(dims[2], dims[1], dims[0]).mean(axis=(0, 1))
+
+    d0 = s.diag(0)
+    p0 = by_profile()
+    s.step(500)
+    d = s.diag(0)
+    assert d["flags"] == 0 and d["count"].tolist() == d0["count"].tolist()
+    assert abs(d["W_B"][1] / d0["W_B"][1] - 1.0) < 1e-3
+    assert np.abs(by_profile() - p0).max() < 1e-2 * hp_b0
+    s.close()
+
+
 def test_autotune_picks_a_working_configuration():
     from paper_1308_5892_amd import pic as P
     spec = W.ENSEMBLE_SMALL

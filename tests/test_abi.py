@@ -79,9 +79,17 @@ def test_plan_sizes(P):
     assert a > 16 ** 3 * (24 + 24) + 2 * 2 * 32768 * 28
 
 
+def test_plan_accepts_the_largest_box_edges(P):
+    for n in ((2048, 4, 4), (4, 2048, 4), (4, 4, 1024)):
+        assert P.pic_plan(_cfg(P, box={"n": n})) > 0
+
+
 @pytest.mark.parametrize("bad", [
     {"box": {"n": (0, 16, 16)}},
     {"box": {"n": (4096, 4, 4)}},
+    {"box": {"n": (2049, 4, 4)}},            # the packed cell holds 11 + 11 + 10 bits
+    {"box": {"n": (4, 2049, 4)}},
+    {"box": {"n": (4, 4, 1025)}},
     {"box": {"tile": (3, 4, 4)}},
     {"box": {"tile": (16, 4, 4)}},
     {"box": {"tile": (8, 8, 8)}},            # the push workgroup would not fit in LDS

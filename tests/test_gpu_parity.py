@@ -247,6 +247,44 @@ def test_tiny_and_odd_boxes(dims, tile):
     s.close()
 
 
+@pytest.mark.parametrize("fp64,tol", [(False, 1e-5), (True, 1e-11)])
+@pytest.mark.parametrize("dims", [(2048, 2, 2), (2, 2048, 2), (2, 2, 1024)])
+def test_largest_box_edges(dims, fp64, tol):
+    # the largest edge the packed cell holds on each axis, with a quarter of
+    # the particles in the last two cells along it, streaming through the
+    # periodic boundary at the top index, and a quarter in the first two
+    rng = np.random.default_rng(17)
+    a = int(np.argmax(dims))
+    n = 4 * int(np.prod(dims))
+    tile = [2, 2, 2]
+    tile[a] = 8
+    s = G.sim(dims, 10.0, 8.0, [n, n], fp64=fp64, tile=tuple(tile))
+    st = G.oracle_state(dims, 10.0, 8.0)
+    parts = []
+    for sp in range(2):
+        x, u = _random_particles(rng, dims, n)
+        q = n // 4
+        x[:q, a] = dims[a] - 2.0 * rng.uniform(0, 1, q)
+        u[:q, a] = np.abs(u[:q, a]) + 0.5
+        x[q:2 * q, a] = 2.0 * rng.uniform(0, 1, q)
+        u[q:2 * q, a] = -np.abs(u[q:2 * q, a]) - 0.5
+        parts.append((x, u))
+    G.start(s, st, parts, fp64=fp64)
+    s.step(10)
+    st.step(10)
+    for sp in range(2):
+        x, u, _ = s.particles(0, sp)
+        assert len(x) == n
+        assert G.u_rel_err(u, st.u[st.species == sp], 1e-2).max() < tol
+        assert np.abs(G.wrap_delta(x, st.x[st.species == sp], dims)).max() < 100 * tol
+        assert np.all((x >= 0) & (x < np.array(dims)))
+    e1, _, _ = s.fields(0)
+    assert np.max(np.abs(e1 - st.e)) < (1e-11 if fp64 else 1e-4) * np.abs(st.e).max()
+    d = s.diag(0)
+    assert d["flags"] == 0
+    s.close()
+
+
 def test_empty_plasma_and_zero_steps():
     s = G.sim((8, 8, 8), 10.0, 2.0, [0, 0])
     s.step(0)

@@ -272,7 +272,8 @@ def test_ensemble_in_one_launch(fp64, tol):
 
 # ----------------------------------------------------------- full sizes
 
-def _one_step_sampled(s, box, dims, dt, n_x, rho0, species, parts, e0, b0, rng, nsample=1024, nfaces=12):
+def _one_step_sampled(s, box, dims, dt, n_x, rho0, species, parts, e0, b0, rng, nsample=1024, nfaces=12,
+                      step=True):
     """One step of the full-size state (parts, e0, b0: already in storage
     form, also held by the GPU context) checked on sampled outputs the oracle
     computes one by one from the same inputs: momenta and positions of sampled
@@ -283,7 +284,8 @@ def _one_step_sampled(s, box, dims, dt, n_x, rho0, species, parts, e0, b0, rng, 
     alpha0 = 2.0 / (n_x * n_x * rho0)
     kq = [q / m for q, m in species]
     sgn = [np.sign(q) for q, _ in species]
-    s.step(1)
+    if step:
+        s.step(1)
     e1, b1, _ = s.fields(box)
     # b: no current, a plain stencil update of the inputs
     bref = O.advance_b(dims, dt, e0, b0)
@@ -414,6 +416,51 @@ def test_full_size_harris_512x256x4():
     del st
     _full_size_check(s, dims, w["dt"], w["n_x"], w["rho0"], species, parts, e0, b0, 3,
                      2.0 / (w["n_x"] ** 2 * w["rho0"]) * w["ppc"])
+    s.close()
+
+
+@pytest.mark.slow
+def test_full_size_ensemble_256_boxes():
+    # The ensemble workload at full size (256 boxes, 2.0e8 particles, device
+    # loads) advanced in one launch.  Boxes are independent, so the oracle
+    # checks a few of them from their own state: the one with most particles,
+    # the hottest, the smallest and one at random, each read back before the
+    # step and checked on sampled particles, b everywhere and sampled faces of
+    # the current.  Then 9 more steps: no particle lost in any box, and the
+    # Gauss residual of every box at roundoff.
+    from paper_1308_5892_amd import pic as P
+    spec = W.ENSEMBLE
+    blist = W.ensemble_boxes(spec)
+    boxes = []
+    for bx in blist:
+        n = int(np.prod(bx["dims"])) * bx["ppc"]
+        boxes.append({"n": bx["dims"], "n_x": spec["n_x"], "rho0": 2.0 * bx["ppc"], "max_particles": [n, n],
+                      "tile": (4, 4, 4)})
+    s = P.Simulation(boxes, G.PAIR, spec["dt"], track_ids=True, sort_interval=50)
+    for i, bx in enumerate(blist):
+        s.load(i, 0, 1, (bx["theta"], 0.0, 1), (bx["theta"], 0.0, 1), bx["ppc"], seed=bx["seed"])
+    s.step(0)
+    npart = [int(np.prod(bx["dims"])) * bx["ppc"] for bx in blist]
+    rng = np.random.default_rng(9)
+    pick = [int(np.argmax(npart)), int(np.argmax([bx["theta"] for bx in blist])), int(np.argmin(npart)),
+            int(rng.integers(len(blist)))]
+    states = {}
+    for i in pick:
+        parts = [s.particles(i, sp)[:2] for sp in range(2)]
+        e0, b0, _ = s.fields(i)
+        states[i] = (parts, e0, b0)
+    s.step(1)
+    for i in pick:
+        bx = blist[i]
+        parts, e0, b0 = states[i]
+        _one_step_sampled(s, i, bx["dims"], spec["dt"], spec["n_x"], 2.0 * bx["ppc"], G.PAIR, parts, e0, b0, rng,
+                          nsample=512, nfaces=6 if npart[i] > 4_000_000 else 12, step=False)
+    s.step(9)
+    for i, bx in enumerate(blist):
+        d = s.diag(i)
+        assert d["flags"] == 0
+        assert d["count"].tolist() == [npart[i], npart[i]], i
+        assert d["gauss_max"] < 1e-4 * 2.0 / (spec["n_x"] ** 2 * 2 * bx["ppc"]) * bx["ppc"], (i, d["gauss_max"])
     s.close()
 
 

@@ -6,7 +6,8 @@ tile, Yee updates of b and e, periodic counting-sort repacks).  The headline
 workload (the default) is the thermal pair plasma: 64^3 cells, 64 pairs per
 cell (33.5 M particles), theta = 0.1, dt = 0.5, n_x = 10.  --workload selects
 one of the other families instead: counter-streaming beams 256x256x4, the
-double Harris sheet 512x256x4, or the ensemble of 256 boxes in one launch.
+double Harris sheet 512x256x4, the ensemble of 256 boxes in one launch, or
+the small 16^3 thermal box (8 pairs/cell), which is launch-bound.
 All inputs are synthetic and seeded; they stand in for the paper's thermal,
 beam and current-sheet test problems.
 
@@ -92,8 +93,8 @@ def workload(name, tile, ppc_range=None):
     import pic_inputs as W
     pair = [(-1.0, 1.0), (1.0, 1.0)]
     harris = []
-    if name == "thermal64":
-        w = W.THERMAL64
+    if name in ("thermal64", "thermal16"):
+        w = W.THERMAL64 if name == "thermal64" else W.THERMAL16
         cells = w["dims"][0] * w["dims"][1] * w["dims"][2]
         npairs = w["ppc"] * cells
         boxes = [{"n": w["dims"], "n_x": w["n_x"], "rho0": 2.0 * w["ppc"], "max_particles": [npairs, npairs],
@@ -164,6 +165,7 @@ def make_sim(wl, fp64, sort_interval):
 
 WORKLOAD_TEXT = {
     "thermal64": "thermal pair plasma 64^3, 64 pairs/cell, theta=0.1, dt=0.5, n_x=10",
+    "thermal16": "thermal pair plasma 16^3, 8 pairs/cell, theta=0.1, dt=0.5, n_x=10 (launch-bound; not a roofline case)",
     "beams": "counter-streaming pair beams 256x256x4, gamma=3 along +-x, 32 pairs/cell/beam, theta=0.01, n_x=20",
     "harris": "double Harris sheet 512x256x4, m_i/m_e=25, theta_e=1, 64 pairs/cell at peak, background 0.1, n_x=15",
     "ensemble": "ensemble of 256 periodic thermal boxes, edges 8..32, 4..256 pairs/cell, theta 0.05..1, n_x=10",

@@ -68,86 +68,6 @@ __device__ inline void boris(R hk, const R E[3], const R Bf[3], R u[3])
     u[2] = um2 + (v0 * s1 - v1 * s0) + hk * E[2];
 }
 
-// Charge-conserving deposit of the straight move d -> d + D, in the frame of
-// the start cell (d in [0,1)^3, |D| < 1).  The volume change of the particle
-// cube in the eight grid-B cells is attributed per component as in App. A.3.4
-// (eq. current_dep): dV_a = -D_a (W_b W_c + sigma D_b D_c / 12).  READING (the
-// paper defers cell-crossing moves to references not given): the move is cut
-// at each node plane it crosses, in order of the crossing parameter, and each
-// piece is deposited in its own cell; breakpoints sit exactly on their plane.
-// add(a, ox, oy, oz, v): value v for component a at node (start cell + o).
-template <typename R, typename Add>
-__device__ inline void deposit_move(const R d[3], const R D[3], R scale, Add &&add)
-{
-    R x1[3];
-    int dir[3];
-    R lam[3];
-    for (int a = 0; a < 3; ++a) {
-        x1[a] = d[a] + D[a];
-        dir[a] = x1[a] < R(0) ? -1 : (x1[a] >= R(1) ? 1 : 0);
-        lam[a] = dir[a] != 0 ? (R(dir[a] > 0) - d[a]) * fast_rcp(D[a]) : R(2);
-    }
-    // order the axes by crossing parameter (non-crossing axes last)
-    int o0 = 0, o1 = 1, o2 = 2;
-    if (lam[o1] < lam[o0]) { int t = o0; o0 = o1; o1 = t; }
-    if (lam[o2] < lam[o1]) { int t = o1; o1 = o2; o2 = t; }
-    if (lam[o1] < lam[o0]) { int t = o0; o0 = o1; o1 = t; }
-    const int ord[3] = {o0, o1, o2};
-    const int nb = (dir[0] != 0) + (dir[1] != 0) + (dir[2] != 0);
-    R p[3] = {d[0], d[1], d[2]};
-    int off[3] = {0, 0, 0};
-    int crossed[3] = {0, 0, 0};
-    for (int k = 0; k <= nb; ++k) {
-        R q[3];
-        if (k < nb) {
-            const int ax = ord[k];
-            const R l = lam[ax];
-            for (int a = 0; a < 3; ++a) {
-                if (a == ax) {
-                    q[a] = R(dir[a] > 0);
-                } else {
-                    R v = d[a] + l * D[a];
-                    if (dir[a] > 0) v = crossed[a] ? fmax(v, R(1)) : fmin(v, R(1));
-                    else if (dir[a] < 0) v = crossed[a] ? fmin(v, R(0)) : fmax(v, R(0));
-                    q[a] = v;
-                }
-            }
-        } else {
-            q[0] = x1[0]; q[1] = x1[1]; q[2] = x1[2];
-        }
-        R s[3], dd[3];
-        for (int a = 0; a < 3; ++a) {
-            s[a] = p[a] - R(off[a]);
-            dd[a] = q[a] - p[a];
-        }
-        if (dd[0] != R(0) || dd[1] != R(0) || dd[2] != R(0)) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int b1 = a == 2 ? 0 : a + 1, b2 = a == 0 ? 2 : a - 1;
-                const R m1 = s[b1] + R(0.5) * dd[b1], m2 = s[b2] + R(0.5) * dd[b2];
-                const R w1[2] = {R(1) - m1, m1}, w2[2] = {R(1) - m2, m2};
-                const R K = dd[b1] * dd[b2] * R(1.0 / 12.0);
-                const R sa = scale * dd[a];
-#pragma unroll
-                for (int pp = 0; pp < 2; ++pp)
-#pragma unroll
-                    for (int qq = 0; qq < 2; ++qq) {
-                        const R v = sa * (w1[pp] * w2[qq] + (pp == qq ? K : -K));
-                        int o[3] = {off[0], off[1], off[2]};
-                        o[b1] += pp;
-                        o[b2] += qq;
-                        add(a, o[0], o[1], o[2], v);
-                    }
-            }
-        }
-        if (k < nb) {
-            off[ord[k]] = dir[ord[k]];
-            crossed[ord[k]] = 1;
-        }
-        p[0] = q[0]; p[1] = q[1]; p[2] = q[2];
-    }
-}
-
 // ------------------------------------------------------ global-memory reads
 
 template <typename R>
@@ -174,29 +94,74 @@ __device__ inline R bt_global(const BoxDev<R> &B, int c, int i, int j, int k, R 
     return fld(B.b, B, c, i, j, k) - hdt * curl;
 }
 
-// Node-averaged fields (App. A.3.3; READING: e_c averaged over the two edges
-// along c meeting at the node, b_c over the four faces normal to c) weighted
-// trilinearly at (cell, d).  Slow path: everything read from HBM.
+// Node-averaged field values (App. A.3.3; READING: e_c averaged over the two
+// edges along c that meet at the node, b_c over the four faces normal to c).
+// The tile set-up forms the same sums in the same order from its LDS copy.
+template <typename R>
+__device__ inline R node_avg2(R a, R b) { return R(0.5) * (a + b); }
+template <typename R>
+__device__ inline R node_avg4(R a, R b, R c, R d) { return R(0.25) * (a + b + c + d); }
+
+// Component c (0-2: e, 3-5: b^t) at node (i,j,k), read from HBM.
+template <typename R>
+__device__ inline R node_value_global(const BoxDev<R> &B, int c, int i, int j, int k, R hdt)
+{
+    switch (c) {
+    case 0: return node_avg2(fld(B.e, B, 0, i - 1, j, k), fld(B.e, B, 0, i, j, k));
+    case 1: return node_avg2(fld(B.e, B, 1, i, j - 1, k), fld(B.e, B, 1, i, j, k));
+    case 2: return node_avg2(fld(B.e, B, 2, i, j, k - 1), fld(B.e, B, 2, i, j, k));
+    case 3: return node_avg4(bt_global(B, 0, i, j, k, hdt), bt_global(B, 0, i, j - 1, k, hdt),
+                             bt_global(B, 0, i, j - 1, k - 1, hdt), bt_global(B, 0, i, j, k - 1, hdt));
+    case 4: return node_avg4(bt_global(B, 1, i, j, k, hdt), bt_global(B, 1, i, j, k - 1, hdt),
+                             bt_global(B, 1, i - 1, j, k - 1, hdt), bt_global(B, 1, i - 1, j, k, hdt));
+    default: return node_avg4(bt_global(B, 2, i, j, k, hdt), bt_global(B, 2, i - 1, j, k, hdt),
+                              bt_global(B, 2, i - 1, j - 1, k, hdt), bt_global(B, 2, i, j - 1, k, hdt));
+    }
+}
+
+// The trilinear interpolant of the eight node values of a cell, f[q] at node
+// (q & 1, (q >> 1) & 1, q >> 2), written as c0 + c1 x + c2 y + c3 z + c4 xy +
+// c5 yz + c6 zx + c7 xyz in the in-cell offsets: its coefficients, and its
+// value at d (pxy = d0 d1, pyz = d1 d2, pzx = d2 d0, pxyz = d0 d1 d2).  The
+// tile path and the HBM path both use these two, so the fields a particle
+// sees do not depend on the path it takes.
+template <typename R, typename P>
+__device__ inline void trilinear_coef(const R f[8], P cf)
+{
+    const R ax = f[1] - f[0], ay = f[2] - f[0], az = f[4] - f[0];
+    const R axy = (f[3] - f[2]) - ax, ayz = (f[6] - f[4]) - ay, azx = (f[5] - f[1]) - az;
+    cf[0] = f[0];
+    cf[1] = ax;
+    cf[2] = ay;
+    cf[3] = az;
+    cf[4] = axy;
+    cf[5] = ayz;
+    cf[6] = azx;
+    cf[7] = ((f[7] - f[6]) - (f[5] - f[4])) - axy;
+}
+template <typename R, typename P>
+__device__ inline R trilinear_eval(P k8, const R d[3], R pxy, R pyz, R pzx, R pxyz)
+{
+    return k8[0] + d[0] * k8[1] + d[1] * k8[2] + d[2] * k8[3] + pxy * k8[4] + pyz * k8[5] + pzx * k8[6] +
+           pxyz * k8[7];
+}
+
+// e^t and b^t at (cell, d) from HBM: the node values, the interpolant's
+// coefficients and its value, as the tile path computes them.
 template <typename R>
 __device__ inline void gather_global(const BoxDev<R> &B, int ix, int iy, int iz, const R d[3], R hdt,
                                      R E[3], R Bf[3])
 {
-    for (int a = 0; a < 3; ++a) { E[a] = R(0); Bf[a] = R(0); }
-    for (int kk = 0; kk < 2; ++kk)
-        for (int jj = 0; jj < 2; ++jj)
-            for (int ii = 0; ii < 2; ++ii) {
-                const int i = ix + ii, j = iy + jj, k = iz + kk;
-                const R w = (ii ? d[0] : R(1) - d[0]) * (jj ? d[1] : R(1) - d[1]) * (kk ? d[2] : R(1) - d[2]);
-                E[0] += w * R(0.5) * (fld(B.e, B, 0, i - 1, j, k) + fld(B.e, B, 0, i, j, k));
-                E[1] += w * R(0.5) * (fld(B.e, B, 1, i, j - 1, k) + fld(B.e, B, 1, i, j, k));
-                E[2] += w * R(0.5) * (fld(B.e, B, 2, i, j, k - 1) + fld(B.e, B, 2, i, j, k));
-                Bf[0] += w * R(0.25) * (bt_global(B, 0, i, j, k, hdt) + bt_global(B, 0, i, j - 1, k, hdt) +
-                                        bt_global(B, 0, i, j - 1, k - 1, hdt) + bt_global(B, 0, i, j, k - 1, hdt));
-                Bf[1] += w * R(0.25) * (bt_global(B, 1, i, j, k, hdt) + bt_global(B, 1, i, j, k - 1, hdt) +
-                                        bt_global(B, 1, i - 1, j, k - 1, hdt) + bt_global(B, 1, i - 1, j, k, hdt));
-                Bf[2] += w * R(0.25) * (bt_global(B, 2, i, j, k, hdt) + bt_global(B, 2, i - 1, j, k, hdt) +
-                                        bt_global(B, 2, i - 1, j - 1, k, hdt) + bt_global(B, 2, i, j - 1, k, hdt));
-            }
+    const R pxy = d[0] * d[1], pyz = d[1] * d[2], pzx = d[2] * d[0], pxyz = pxy * d[2];
+    for (int c = 0; c < 6; ++c) {
+        R f[8], cf[8];
+        for (int q = 0; q < 8; ++q)
+            f[q] = node_value_global(B, c, ix + (q & 1), iy + ((q >> 1) & 1), iz + (q >> 2), hdt);
+        trilinear_coef(f, cf);
+        const R v = trilinear_eval(cf, d, pxy, pyz, pzx, pxyz);
+        if (c < 3) E[c] = v;
+        else Bf[c - 3] = v;
+    }
 }
 
 // ------------------------------------------------------------ slot claims
@@ -442,9 +407,15 @@ __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v -
 // (0,0) value is the total minus the other three (taken after rounding to the
 // fixed-point grid in the FP32 form, so each component's four values add up
 // to the rounded total).
-template <typename R>
-__device__ inline void deposit_piece(typename JType<R>::T *jl, int cb, const int (&off)[3][4], const R s[3],
-                                     const R dd[3], R scale)
+// The twelve fluxes of one piece (start offset s in its cell, displacement
+// dd), eq. current_dep with the sign and scale of the species, rounded to the
+// fixed-point current: per component a, the four faces around the cell's
+// a-edge, f = 0 at the cell, 1 one step along b2, 2 one step along b1, 3 both
+// (b1, b2 the two other axes in cyclic order).  The four rounded values of a
+// component add up to the rounded total flux, so a piece moves exactly its
+// charge.  add(a, f, q) receives each rounded value.
+template <typename R, typename Add>
+__device__ inline void piece_fluxes(const R s[3], const R dd[3], R scale, Add &&add)
 {
     const R m[3] = {s[0] + R(0.5) * dd[0], s[1] + R(0.5) * dd[1], s[2] + R(0.5) * dd[2]};
 #pragma unroll
@@ -455,11 +426,18 @@ __device__ inline void deposit_piece(typename JType<R>::T *jl, int cb, const int
         const R t11 = F * PK, t01 = fma(F, m[b2], -t11), t10 = fma(F, m[b1], -t11);
         const auto q11 = quantize(t11), q01 = quantize(t01), q10 = quantize(t10);
         const auto q00 = quantize(F) - q01 - q10 - q11;
-        atomic_add_lds(&jl[cb + off[a][0]], q00);
-        atomic_add_lds(&jl[cb + off[a][1]], q01);
-        atomic_add_lds(&jl[cb + off[a][2]], q10);
-        atomic_add_lds(&jl[cb + off[a][3]], q11);
+        add(a, 0, q00);
+        add(a, 1, q01);
+        add(a, 2, q10);
+        add(a, 3, q11);
     }
+}
+
+template <typename R>
+__device__ inline void deposit_piece(typename JType<R>::T *jl, int cb, const int (&off)[3][4], const R s[3],
+                                     const R dd[3], R scale)
+{
+    piece_fluxes(s, dd, scale, [&](int a, int f, auto q) { atomic_add_lds(&jl[cb + off[a][f]], q); });
 }
 
 template <typename R>
@@ -540,6 +518,94 @@ __device__ inline void crossing_point(const R d[3], const R D[3], const int dir[
         if (dir[a] > 0) v = lam[a] <= l ? fmax(v, R(1)) : fmin(v, R(1));
         else if (dir[a] < 0) v = lam[a] <= l ? fmin(v, R(0)) : fmax(v, R(0));
         q[a] = a == ax ? (dir[a] > 0 ? R(1) : R(0)) : v;
+    }
+}
+
+// Cell of a piece from its start ps to its end pe (home-cell frame): the
+// piece's cell offset, its start in that cell and its displacement.
+template <typename R>
+__device__ inline void piece_frame(const R ps[3], const R pe[3], int offc[3], R sv[3], R dd[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        offc[a] = (int)floor(R(0.5) * (ps[a] + pe[a]));
+        sv[a] = ps[a] - R(offc[a]);
+        dd[a] = pe[a] - ps[a];
+    }
+}
+
+// Charge-conserving deposit of the straight move d -> d + D from the start
+// cell (d in [0,1)^3, |D| < 1), for the particles that take the HBM path.
+// READING (the paper defers cell-crossing moves to references not given): the
+// move is cut at each node plane it crosses, in order of the crossing
+// parameter, and each piece deposits its fluxes (eq. current_dep, App. A.3.4)
+// in its own cell.  The crossings, their order, the breakpoints and the
+// fluxes are computed exactly as the tile path computes them (its first piece
+// at once, the others from the queue), so a move deposits the same integers
+// whichever path it takes.  add(a, ox, oy, oz, q): rounded flux q of
+// component a at node (start cell + o).
+template <typename R, typename Add>
+__device__ inline void deposit_move(const R d[3], const R D[3], R scale, Add &&add)
+{
+    R x1[3], lam[3];
+    int dir[3];
+    move_crossings(d, D, x1, dir, lam);
+    const int nb = (dir[0] != 0) + (dir[1] != 0) + (dir[2] != 0);
+    int o0 = 0, o1 = 1, o2 = 2;
+    R l0 = lam[0], l1 = lam[1], l2 = lam[2];
+    if (l1 < l0) { R t = l0; l0 = l1; l1 = t; int q = o0; o0 = o1; o1 = q; }
+    if (l2 < l1) { R t = l1; l1 = l2; l2 = t; int q = o1; o1 = o2; o2 = q; }
+    if (l1 < l0) { R t = l0; l0 = l1; l1 = t; int q = o0; o0 = o1; o1 = q; }
+    const int ord[3] = {o0, o1, o2};
+    for (int k = 0; k <= nb; ++k) {
+        R ps[3], pe[3];
+        if (k == 0) {
+            ps[0] = d[0]; ps[1] = d[1]; ps[2] = d[2];
+        } else {
+            const int oa = ord[k - 1];
+            crossing_point(d, D, dir, lam, oa, sel3(oa, lam[0], lam[1], lam[2]), ps);
+        }
+        if (k < nb) {
+            const int ob = ord[k];
+            crossing_point(d, D, dir, lam, ob, sel3(ob, lam[0], lam[1], lam[2]), pe);
+        } else {
+            pe[0] = x1[0]; pe[1] = x1[1]; pe[2] = x1[2];
+        }
+        int offc[3];
+        R sv[3], dd[3];
+        piece_frame(ps, pe, offc, sv, dd);
+        piece_fluxes(sv, dd, scale, [&](int a, int f, auto q) {
+            const int b1 = a == 2 ? 0 : a + 1, b2 = a == 0 ? 2 : a - 1;
+            int o[3] = {offc[0], offc[1], offc[2]};
+            if (f & 1) o[b2] += 1;
+            if (f & 2) o[b1] += 1;
+            add(a, o[0], o[1], o[2], q);
+        });
+    }
+}
+
+// The Boris step, the non-finite check and the displacement D = dt u / gamma
+// of the move, shared by the tile and HBM paths.  D stays the rounded product
+// (opaque to the compiler, so that no multiply-add fuses it into d + D): a
+// queued move's crossings are recomputed from the stored (d, D) and must come
+// out identical.
+template <typename R>
+__device__ inline void boris_move(R hk, const R E[3], const R Bf[3], R u[3], R dt, bool valid,
+                                  PIC_GLOBAL uint32_t *flags, R D[3])
+{
+    boris(hk, E, Bf, u);
+    // one test catches NaN and infinity (and |u| beyond 1e15)
+    R u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    if (!(u2 < R(1e30))) {
+        if (valid) atomicOr(flags, PIC_FLAG_NONFINITE);
+        u[0] = u[1] = u[2] = R(0);
+        u2 = R(0);
+    }
+    const R ig = dt * fast_rsqrt(R(1) + u2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        D[a] = ig * u[a];
+        asm volatile("" : "+v"(D[a]));
     }
 }
 
@@ -635,13 +701,8 @@ __device__ void push_overflow(const BoxDev<R> &B, int kblk, const StepConst<R> &
             R E[3], Bf[3];
             if (valid) gather_global(B, ix, iy, iz, d, hdt, E, Bf);
             else for (int a = 0; a < 3; ++a) { E[a] = R(0); Bf[a] = R(0); }
-            boris(hk, E, Bf, u);
-            if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]))) {
-                if (valid) atomicOr(C.flags, PIC_FLAG_NONFINITE);
-                u[0] = u[1] = u[2] = R(0);
-            }
-            const R ig = C.dt * fast_rsqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            R D[3] = {ig * u[0], ig * u[1], ig * u[2]};
+            R D[3];
+            boris_move(hk, E, Bf, u, C.dt, valid, C.flags, D);
             // a move through a conducting wall (App. A.4): deposit up to the
             // wall, then the mirrored rest; the particle ends at P2 + D2
             R D1[3], P2[3], D2[3];
@@ -650,19 +711,19 @@ __device__ void push_overflow(const BoxDev<R> &B, int kblk, const StepConst<R> &
                                        D2, u);
             if (valid) {
                 JT *J = B.J;
-                auto put_j = [&](int a, int ox, int oy, int oz, R v) {
+                auto put_j = [&](int a, int ox, int oy, int oz, JT q) {
+                    if (q == JT(0)) return;
                     const int i = wrap_idx(ix + ox, B.n[0]), j = wrap_idx(iy + oy, B.n[1]),
                               k = wrap_idx(iz + oz, B.n[2]);
-                    atomic_add_global(&J[a * B.nc + i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)],
-                                      quantize(v));
+                    atomic_add_global(&J[a * B.nc + i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)], q);
                 };
                 if (hitw) {
                     deposit_move(d, D1, scale, put_j);
                     R Q2[3] = {P2[0], P2[1], P2[2]};
                     int s2[3];
                     wall_rest_start(B.wall, Q2, s2);
-                    deposit_move(Q2, D2, scale, [&](int a, int ox, int oy, int oz, R v) {
-                        put_j(a, s2[0] + ox, s2[1] + oy, s2[2] + oz, v);
+                    deposit_move(Q2, D2, scale, [&](int a, int ox, int oy, int oz, JT q) {
+                        put_j(a, s2[0] + ox, s2[1] + oy, s2[2] + oz, q);
                     });
                 } else {
                     deposit_move(d, D, scale, put_j);
@@ -780,12 +841,12 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             // raw coordinates of node (i,j,k) are (i+1, j+1, k+1)
             const int pe = (i + 1) + JX * (j + 1) + JXY * (k + 1);
             const int pb = (i + 1) + BX * (j + 1) + BXY * (k + 1);
-            node[q] = R(0.5) * (ex[pe - 1] + ex[pe]);
-            node[g.NN + q] = R(0.5) * (ey[pe - JX] + ey[pe]);
-            node[2 * g.NN + q] = R(0.5) * (ez[pe - JXY] + ez[pe]);
-            node[3 * g.NN + q] = R(0.25) * (bx[pb] + bx[pb - BX] + bx[pb - BX - BXY] + bx[pb - BXY]);
-            node[4 * g.NN + q] = R(0.25) * (by[pb] + by[pb - BXY] + by[pb - 1 - BXY] + by[pb - 1]);
-            node[5 * g.NN + q] = R(0.25) * (bz[pb] + bz[pb - 1] + bz[pb - 1 - BX] + bz[pb - BX]);
+            node[q] = node_avg2(ex[pe - 1], ex[pe]);
+            node[g.NN + q] = node_avg2(ey[pe - JX], ey[pe]);
+            node[2 * g.NN + q] = node_avg2(ez[pe - JXY], ez[pe]);
+            node[3 * g.NN + q] = node_avg4(bx[pb], bx[pb - BX], bx[pb - BX - BXY], bx[pb - BXY]);
+            node[4 * g.NN + q] = node_avg4(by[pb], by[pb - BXY], by[pb - 1 - BXY], by[pb - 1]);
+            node[5 * g.NN + q] = node_avg4(bz[pb], bz[pb - 1], bz[pb - 1 - BX], bz[pb - BX]);
         }
     }
     __syncthreads();
@@ -805,18 +866,8 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 const R *F = node + c * g.NN + m;
-                const R f000 = F[0], f100 = F[1], f010 = F[NX], f110 = F[1 + NX];
-                const R f001 = F[NXY], f101 = F[1 + NXY], f011 = F[NX + NXY], f111 = F[1 + NX + NXY];
-                const R ax = f100 - f000, ay = f010 - f000, az = f001 - f000;
-                const R axy = (f110 - f010) - ax, ayz = (f011 - f001) - ay, azx = (f101 - f100) - az;
-                cf[8 * c + 0] = f000;
-                cf[8 * c + 1] = ax;
-                cf[8 * c + 2] = ay;
-                cf[8 * c + 3] = az;
-                cf[8 * c + 4] = axy;
-                cf[8 * c + 5] = ayz;
-                cf[8 * c + 6] = azx;
-                cf[8 * c + 7] = ((f111 - f011) - (f101 - f001)) - axy;
+                const R f[8] = {F[0], F[1], F[NX], F[1 + NX], F[NXY], F[1 + NXY], F[NX + NXY], F[1 + NX + NXY]};
+                trilinear_coef(f, cf + 8 * c);
             }
         }
     }
@@ -896,12 +947,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             else { pe[0] = x1[0]; pe[1] = x1[1]; pe[2] = x1[2]; }
             int offc[3];
             R sv[3], dd[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                offc[a] = (int)floor(R(0.5) * (ps[a] + pe[a]));   // cell of the piece
-                sv[a] = ps[a] - R(offc[a]);
-                dd[a] = pe[a] - ps[a];
-            }
+            piece_frame(ps, pe, offc, sv, dd);
             const int cb = (w & 0x7fffffff) + offc[0] + __mul24(JX, offc[1]) + __mul24(JXY, offc[2]);
             const R sc = w < 0 ? -qscale_bits<R>() : qscale_bits<R>();
             deposit_piece<R>(jl, cb, joff, sv, dd, sc);
@@ -955,29 +1001,12 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                 const R pxy = d[0] * d[1], pyz = d[1] * d[2], pzx = d[2] * d[0], pxyz = pxy * d[2];
                 R F[6];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    const R *k8 = cf + 8 * c;
-                    F[c] = k8[0] + d[0] * k8[1] + d[1] * k8[2] + d[2] * k8[3] + pxy * k8[4] + pyz * k8[5] +
-                           pzx * k8[6] + pxyz * k8[7];
-                }
+                for (int c = 0; c < 6; ++c) F[c] = trilinear_eval(cf + 8 * c, d, pxy, pyz, pzx, pxyz);
                 E[0] = F[0]; E[1] = F[1]; E[2] = F[2];
                 Bf[0] = F[3]; Bf[1] = F[4]; Bf[2] = F[5];
             }
-            boris(hk, E, Bf, u);
-            // one test catches NaN and infinity (and |u| beyond 1e15)
-            R u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-            if (!(u2 < R(1e30))) {
-                if (valid) atomicOr(C.flags, PIC_FLAG_NONFINITE);
-                u[0] = u[1] = u[2] = R(0);
-                u2 = R(0);
-            }
-            const R ig = C.dt * fast_rsqrt(R(1) + u2);
-            R D[3] = {ig * u[0], ig * u[1], ig * u[2]};
-            // D stays the rounded product (no multiply-add into x1 = d + D):
-            // a queued move's crossings are recomputed from the stored (d, D)
-            // and must come out identical
-#pragma unroll
-            for (int a = 0; a < 3; ++a) asm volatile("" : "+v"(D[a]));
+            R D[3];
+            boris_move(hk, E, Bf, u, C.dt, valid, C.flags, D);
 
             // node planes crossed by the move (end x1 in the home-cell frame)
             R x1[3], lam[3];
@@ -1073,11 +1102,11 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                 deposit_piece<R>(jl, jb, joff, d, dd, scale);
             } else if (valid) {
                 PIC_GLOBAL JT *J = B.J;
-                deposit_move(d, D, scale, [&](int a, int ox, int oy, int oz, R v) {
+                deposit_move(d, D, scale, [&](int a, int ox, int oy, int oz, JT q) {
+                    if (q == JT(0)) return;
                     const int i = wrap_idx(ix + ox, B.n[0]), j = wrap_idx(iy + oy, B.n[1]),
                               k = wrap_idx(iz + oz, B.n[2]);
-                    atomic_add_global(&J[a * B.nc + i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)],
-                                      quantize(v));
+                    atomic_add_global(&J[a * B.nc + i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)], q);
                 });
             }
             put(valid && inside && nb > 0, jb | sgnbit, 1 | (nb << 2) | (o0 << 4) | (o1 << 6) | (o2 << 8), d, D);
@@ -1099,11 +1128,11 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                 put(hitw && inside, jb2 | sgnbit, 0 | (nb2 << 2) | (q0 << 4) | (q1 << 6) | (q2 << 8), P2, D2);
                 if (hitw && !inside) {
                     PIC_GLOBAL JT *J = B.J;
-                    deposit_move(P2, D2, scale, [&](int a, int ox, int oy, int oz, R v) {
+                    deposit_move(P2, D2, scale, [&](int a, int ox, int oy, int oz, JT q) {
+                        if (q == JT(0)) return;
                         const int i = wrap_idx(ix + s2[0] + ox, B.n[0]), j = wrap_idx(iy + s2[1] + oy, B.n[1]),
                                   k = wrap_idx(iz + s2[2] + oz, B.n[2]);
-                        atomic_add_global(&J[a * B.nc + i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)],
-                                          quantize(v));
+                        atomic_add_global(&J[a * B.nc + i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)], q);
                     });
                 }
                 while (qcount >= 64) drain();
@@ -1538,12 +1567,12 @@ __global__ void __launch_bounds__(kBlock) diag_particles_kernel(const BoxDev<R> 
     TileGeom<R> g{};
     if (in_tile) {
         g = tile_geom<R>(B, it.tile);
-        // node-averaged e (App. A.3.3): the same values the HBM gather forms
+        // node-averaged e (App. A.3.3)
         for (int q = tid; q < g.NN; q += kBlock) {
             const int i = g.o[0] + q % g.NX, j = g.o[1] + (q / g.NX) % g.NY, k = g.o[2] + q / (g.NX * g.NY);
-            sE[q] = R(0.5) * (fld(B.e, B, 0, i - 1, j, k) + fld(B.e, B, 0, i, j, k));
-            sE[g.NN + q] = R(0.5) * (fld(B.e, B, 1, i, j - 1, k) + fld(B.e, B, 1, i, j, k));
-            sE[2 * g.NN + q] = R(0.5) * (fld(B.e, B, 2, i, j, k - 1) + fld(B.e, B, 2, i, j, k));
+            sE[q] = node_value_global(B, 0, i, j, k, R(0));
+            sE[g.NN + q] = node_value_global(B, 1, i, j, k, R(0));
+            sE[2 * g.NN + q] = node_value_global(B, 2, i, j, k, R(0));
             srho[q] = 0.0;
         }
     }
@@ -1566,18 +1595,17 @@ __global__ void __launch_bounds__(kBlock) diag_particles_kernel(const BoxDev<R> 
             R E[3];
             int nb = 0;
             if (in_tile) {
+                // the cell's trilinear interpolant, as the push evaluates it
                 nb = (ix - g.o[0]) + g.NX * ((iy - g.o[1]) + g.NY * (iz - g.o[2]));
-                E[0] = E[1] = E[2] = R(0);
-                for (int kk = 0; kk < 2; ++kk)
-                    for (int jj = 0; jj < 2; ++jj)
-                        for (int ii = 0; ii < 2; ++ii) {
-                            const R w = (ii ? d[0] : R(1) - d[0]) * (jj ? d[1] : R(1) - d[1]) *
-                                        (kk ? d[2] : R(1) - d[2]);
-                            const int n = nb + ii + g.NX * (jj + g.NY * kk);
-                            E[0] += w * sE[n];
-                            E[1] += w * sE[g.NN + n];
-                            E[2] += w * sE[2 * g.NN + n];
-                        }
+                const R pxy = d[0] * d[1], pyz = d[1] * d[2], pzx = d[2] * d[0], pxyz = pxy * d[2];
+                for (int c = 0; c < 3; ++c) {
+                    const R *F = sE + c * g.NN + nb;
+                    const int NX = g.NX, NXY = g.NX * g.NY;
+                    const R f[8] = {F[0], F[1], F[NX], F[1 + NX], F[NXY], F[1 + NXY], F[NX + NXY], F[1 + NX + NXY]};
+                    R cf[8];
+                    trilinear_coef(f, cf);
+                    E[c] = trilinear_eval(cf, d, pxy, pyz, pzx, pxyz);
+                }
             } else {
                 R Bf[3];
                 gather_global(B, ix, iy, iz, d, hdt, E, Bf);

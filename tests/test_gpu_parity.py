@@ -185,6 +185,63 @@ def test_gauss_law_and_determinism_fp32():
     assert d["gauss_max"] < 1e-4 * rho_scale, d["gauss_max"]
 
 
+def test_runs_are_bitwise_identical_when_particles_overflow():
+    # Which particles land in the overflow region (and take the HBM gather and
+    # deposit instead of the tile's LDS ones) depends on the order of the slot
+    # claims, which differs from run to run.  Both paths compute the same
+    # arithmetic, so two runs still agree bit for bit: particles, e and b.
+    def run():
+        rng = np.random.default_rng(11)
+        dims, n = (16, 8, 8), 6000
+        s = G.sim(dims, 10.0, 16.0, [n, n], headroom=1.05)
+        st = G.oracle_state(dims, 10.0, 16.0)
+        parts = []
+        for sp in range(2):
+            x = rng.uniform(0, 1, (n, 3)) * np.array([4.0, 8.0, 8.0])
+            u = 0.05 * rng.standard_normal((n, 3))
+            u[: n // 10, 0] += 3.0
+            parts.append((x, u))
+        G.start(s, st, parts)
+        seen = 0
+        for _ in range(12):
+            s.step(1)
+            seen = max(seen, int(s.diag(0)["n_overflow"].sum()))
+        out = [s.particles(0, sp) for sp in range(2)] + [s.fields(0)[:2]]
+        s.close()
+        return out, seen
+
+    (a, seen), (b, _) = run(), run()
+    assert seen > 0
+    for sp in range(2):
+        for k in range(3):
+            assert np.array_equal(a[sp][k], b[sp][k]), (sp, k)
+    assert np.array_equal(a[2][0], b[2][0]) and np.array_equal(a[2][1], b[2][1])
+
+
+def test_long_magnetized_runs_are_bitwise_identical():
+    # a hot electron-ion plasma in a uniform b for 2000 steps with repacks
+    # every 50 steps: the whole state of two runs agrees bit for bit
+    def run():
+        n_x, ppc = 25, 8
+        n = n_x ** 3
+        s = G.sim((n_x,) * 3, float(n_x), 16.0, [ppc * n] * 2, dt=2 * np.pi * n_x / 1000,
+                  species=[(-1.0, 1.0), (1.0, 49.0)], sort_interval=50)
+        b = np.zeros(3 * n)
+        b[2 * n:] = 1.0 / n_x
+        s.set_fields(0, np.zeros(3 * n), b)
+        s.load(0, 0, 1, (0.0016, 0.0, 2), (0.0016 / 49, 0.0, 2), ppc, seed=11)
+        s.step(2000)
+        out = [s.particles(0, sp) for sp in range(2)] + [s.fields(0)[:2]]
+        s.close()
+        return out
+
+    a, b = run(), run()
+    for sp in range(2):
+        for k in range(3):
+            assert np.array_equal(a[sp][k], b[sp][k]), (sp, k)
+    assert np.array_equal(a[2][0], b[2][0]) and np.array_equal(a[2][1], b[2][1])
+
+
 def test_gauss_law_fp64_at_roundoff():
     dims, ppc = (12, 10, 8), 6
     npairs = ppc * int(np.prod(dims))

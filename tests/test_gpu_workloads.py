@@ -119,6 +119,69 @@ def test_thermal64_long_run_statistics_fp32_vs_fp64():
         assert abs(pk[True] / om_theory - 1.0) < 0.02, (a, pk, om_theory)
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("row", [0, 1, 2, 3], ids=["wce0.5", "wce1", "wce2", "wce4"])
+def test_magnetized_thermal_modes_match_table1(row):
+    # The paper's runs of Table 1 (Sect. 3.1.2) at their own parameters: a
+    # thermal electron-ion plasma (m_i/m_e = 49, T_i = T_e, v_th = 0.04 c) in
+    # a uniform b along z, a box of n_x^3 cells, 100 plasma periods.  The
+    # spectrum of the total electron momentum (Sect. 3.1) along b peaks at the
+    # plasma pulsation, and across b at the left and right cut-offs; the
+    # peaks must fall within twice the paper's spectral precision of the
+    # values its own runs printed.  Each across-b peak is searched on its side
+    # of the midpoint between the cold-plasma cut-offs
+    # omega_L,R = (sqrt(omega_ce^2 + 4) -/+ omega_ce) / 2 (units of omega_pe).
+    import json
+    import os
+    from paper_1308_5892_amd import pic as P
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1_thermal_runs.json")))
+    r = gold["rows"][row]
+    n_x, n_t, wce = r["n_x"], r["n_t"], r["omega_ce"]
+    ppc = r["rho_sp"] // 2
+    th_e = gold["v_th_e"] ** 2
+    dims = (n_x, n_x, n_x)
+    n = n_x ** 3
+    dt = 2 * np.pi * n_x / n_t
+    s = P.Simulation([{"n": dims, "n_x": float(n_x), "rho0": float(r["rho_sp"]), "max_particles": [ppc * n] * 2}],
+                     [(-1.0, 1.0), (1.0, float(gold["mi_over_me"]))], dt, sort_interval=50)
+    b = np.zeros(3 * n)
+    b[2 * n:] = wce / n_x
+    s.set_fields(0, np.zeros(3 * n), b)
+    s.load(0, 0, 1, (th_e, 0.0, 2), (th_e / gold["mi_over_me"], 0.0, 2), ppc, seed=11)
+    every = n_t // 40
+    series = []
+    for k in range(0, gold["duration_Tpe"] * n_t + 1, every):
+        if k:
+            s.step(every)
+        series.append(s.diag(0)["P"][0])
+    assert s.diag(0)["flags"] == 0
+    s.close()
+    series = np.array(series)
+
+    def spectrum(x):
+        x = x - x.mean()
+        pad = 8 * len(x)
+        F = np.abs(np.fft.rfft(x * np.hanning(len(x)), pad)) ** 2
+        return 2 * np.pi * np.fft.rfftfreq(pad, d=every * dt) * n_x, F   # omega in units of omega_pe
+
+    def peak(om, F, lo, hi):
+        m = (om > lo) & (om < hi)
+        return om[m][np.argmax(F[m])]
+
+    tol = 2 * gold["spectral_resolution"]
+    om, Fz = spectrum(series[:, 2])
+    assert abs(peak(om, Fz, 0.3, 3.0) - r["omega_par"]) <= tol
+    _, Fx = spectrum(series[:, 0])
+    _, Fy = spectrum(series[:, 1])
+    wl = 0.5 * (np.sqrt(wce ** 2 + 4) - wce)
+    wr = 0.5 * (np.sqrt(wce ** 2 + 4) + wce)
+    mid = 0.5 * (wl + wr)
+    got = [peak(om, Fx + Fy, 0.1, mid), peak(om, Fx + Fy, mid, 2 * wr)]
+    print(f"omega_ce {wce}: along b {peak(om, Fz, 0.3, 3.0):.3f}, across b {got[0]:.3f}, {got[1]:.3f}")
+    assert abs(got[0] - r["omega_perp"][0]) <= tol, got
+    assert abs(got[1] - r["omega_perp"][1]) <= tol, got
+
+
 def test_energy_curve_fp64_form_follows_oracle_100_steps():
     w = W.THERMAL16
     dims, ppc = w["dims"], w["ppc"]

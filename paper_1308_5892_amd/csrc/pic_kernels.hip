@@ -339,9 +339,9 @@ __device__ inline TileGeom<R> tile_geom(const BoxDev<R> &B, int T)
 // Per-wave queue of unfinished moves (LDS ring buffer): a move that crosses
 // node planes deposits its first piece at once and waits here for the rest;
 // the wave deposits the next piece of 64 queued moves at a time and puts back
-// those that still have pieces left.  An entry holds the move (start offsets
-// and displacement), the LDS index of its home cell with the species sign, and
-// its crossing order, piece count and next piece.
+// those that still have pieces left.  An entry holds the start of the next
+// piece and the end of the move (home-cell frame), the LDS index of the home
+// cell with the species sign, and the meta word of the move (move_meta).
 constexpr int kQCap = 128;
 constexpr int kWaves = kBlock / 64;
 
@@ -521,6 +521,46 @@ __device__ inline void crossing_point(const R d[3], const R D[3], const int dir[
     }
 }
 
+// Meta word of a queued move: next piece k (bits 0-1), crossings nb (2-3),
+// the crossing axes in order o0, o1, o2 (4-9), and per axis the crossing
+// direction + 1 (10-15).
+__device__ inline int move_meta(int k, int nb, int o0, int o1, int o2, const int dir[3])
+{
+    return k | (nb << 2) | (o0 << 4) | (o1 << 6) | (o2 << 8) | ((dir[0] + 1) << 10) | ((dir[1] + 1) << 12) |
+           ((dir[2] + 1) << 14);
+}
+
+// Breakpoint of crossing k of a move, continued from the previous breakpoint
+// ps towards the move's end x1 (home-cell frame): the crossing axis sits on
+// its plane, an axis already crossed stays on the far side of its plane, one
+// still to cross on the near side.  Every later breakpoint of a move is
+// computed this way from the one before, on the tile path and on the HBM
+// path alike, so consecutive pieces share their breakpoints exactly and the
+// last piece ends exactly at the particle's new position.
+template <typename R>
+__device__ inline void chain_point(const R ps[3], const R x1[3], int meta, int k, R pe[3])
+{
+    const int ax = (meta >> (4 + 2 * k)) & 3;
+    int crossed = 0;
+    if (k > 0) crossed |= 1 << ((meta >> 4) & 3);
+    if (k > 1) crossed |= 1 << ((meta >> 6) & 3);
+    const R Dp[3] = {x1[0] - ps[0], x1[1] - ps[1], x1[2] - ps[2]};
+    const R plane = ((meta >> (10 + 2 * ax)) & 3) == 2 ? R(1) : R(0);
+    // the parameter of the crossing along the rest of the move; a rest that
+    // no longer moves along the axis (0 * inf) gives 0
+    R l = (plane - sel3(ax, ps[0], ps[1], ps[2])) * fast_rcp(sel3(ax, Dp[0], Dp[1], Dp[2]));
+    l = fmin(fmax(l, R(0)), R(1));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int da = ((meta >> (10 + 2 * a)) & 3) - 1;
+        const bool far = (crossed >> a) & 1;
+        R v = fma(l, Dp[a], ps[a]);
+        if (da > 0) v = far ? fmax(v, R(1)) : fmin(v, R(1));
+        else if (da < 0) v = far ? fmin(v, R(0)) : fmax(v, R(0));
+        pe[a] = a == ax ? plane : v;
+    }
+}
+
 // Cell of a piece from its start ps to its end pe (home-cell frame): the
 // piece's cell offset, its start in that cell and its displacement.
 template <typename R>
@@ -534,43 +574,18 @@ __device__ inline void piece_frame(const R ps[3], const R pe[3], int offc[3], R 
     }
 }
 
-// Charge-conserving deposit of the straight move d -> d + D from the start
-// cell (d in [0,1)^3, |D| < 1), for the particles that take the HBM path.
-// READING (the paper defers cell-crossing moves to references not given): the
-// move is cut at each node plane it crosses, in order of the crossing
-// parameter, and each piece deposits its fluxes (eq. current_dep, App. A.3.4)
-// in its own cell.  The crossings, their order, the breakpoints and the
-// fluxes are computed exactly as the tile path computes them (its first piece
-// at once, the others from the queue), so a move deposits the same integers
-// whichever path it takes.  add(a, ox, oy, oz, q): rounded flux q of
-// component a at node (start cell + o).
+// The pieces k, k+1, ..., nb of a queued move, from breakpoint ps to the
+// move's end x1 (see chain_point), as the queue deposits them.
+// add(a, ox, oy, oz, q): rounded flux q of component a at node (cell + o).
 template <typename R, typename Add>
-__device__ inline void deposit_move(const R d[3], const R D[3], R scale, Add &&add)
+__device__ inline void deposit_chain(const R ps0[3], const R x1[3], int meta, int k, R scale, Add &&add)
 {
-    R x1[3], lam[3];
-    int dir[3];
-    move_crossings(d, D, x1, dir, lam);
-    const int nb = (dir[0] != 0) + (dir[1] != 0) + (dir[2] != 0);
-    int o0 = 0, o1 = 1, o2 = 2;
-    R l0 = lam[0], l1 = lam[1], l2 = lam[2];
-    if (l1 < l0) { R t = l0; l0 = l1; l1 = t; int q = o0; o0 = o1; o1 = q; }
-    if (l2 < l1) { R t = l1; l1 = l2; l2 = t; int q = o1; o1 = o2; o2 = q; }
-    if (l1 < l0) { R t = l0; l0 = l1; l1 = t; int q = o0; o0 = o1; o1 = q; }
-    const int ord[3] = {o0, o1, o2};
-    for (int k = 0; k <= nb; ++k) {
-        R ps[3], pe[3];
-        if (k == 0) {
-            ps[0] = d[0]; ps[1] = d[1]; ps[2] = d[2];
-        } else {
-            const int oa = ord[k - 1];
-            crossing_point(d, D, dir, lam, oa, sel3(oa, lam[0], lam[1], lam[2]), ps);
-        }
-        if (k < nb) {
-            const int ob = ord[k];
-            crossing_point(d, D, dir, lam, ob, sel3(ob, lam[0], lam[1], lam[2]), pe);
-        } else {
-            pe[0] = x1[0]; pe[1] = x1[1]; pe[2] = x1[2];
-        }
+    const int nb = (meta >> 2) & 3;
+    R ps[3] = {ps0[0], ps0[1], ps0[2]};
+    for (; k <= nb; ++k) {
+        R pe[3];
+        if (k < nb) chain_point(ps, x1, meta, k, pe);
+        else { pe[0] = x1[0]; pe[1] = x1[1]; pe[2] = x1[2]; }
         int offc[3];
         R sv[3], dd[3];
         piece_frame(ps, pe, offc, sv, dd);
@@ -581,7 +596,72 @@ __device__ inline void deposit_move(const R d[3], const R D[3], R scale, Add &&a
             if (f & 2) o[b1] += 1;
             add(a, o[0], o[1], o[2], q);
         });
+        ps[0] = pe[0]; ps[1] = pe[1]; ps[2] = pe[2];
     }
+}
+
+// Crossings of the move d -> d + D, their order and the meta word (next piece
+// k), as the push computes them.
+template <typename R>
+__device__ inline int move_order(const R d[3], const R D[3], int k, R x1[3], int dir[3], R lam[3], int &o0,
+                                 R &l0)
+{
+    move_crossings(d, D, x1, dir, lam);
+    const int nb = (dir[0] != 0) + (dir[1] != 0) + (dir[2] != 0);
+    int q0 = 0, q1 = 1, q2 = 2;
+    R m0 = lam[0], m1 = lam[1], m2 = lam[2];
+    if (m1 < m0) { R t = m0; m0 = m1; m1 = t; int q = q0; q0 = q1; q1 = q; }
+    if (m2 < m1) { R t = m1; m1 = m2; m2 = t; int q = q1; q1 = q2; q2 = q; }
+    if (m1 < m0) { R t = m0; m0 = m1; m1 = t; int q = q0; q0 = q1; q1 = q; }
+    o0 = q0;
+    l0 = m0;
+    return move_meta(k, nb, q0, q1, q2, dir);
+}
+
+// Charge-conserving deposit of the straight move d -> d + D from the start
+// cell (d in [0,1)^3, |D| < 1), for the particles that take the HBM path.
+// READING (the paper defers cell-crossing moves to references not given): the
+// move is cut at each node plane it crosses, in order of the crossing
+// parameter, and each piece deposits its fluxes (eq. current_dep, App. A.3.4)
+// in its own cell.  The first breakpoint comes from d and the crossing
+// parameter, the later ones from chain_point, the fluxes from piece_fluxes:
+// exactly as the tile path computes them (its first piece at once, the
+// others from the queue), so a move deposits the same integers whichever
+// path it takes.  add(a, ox, oy, oz, q): rounded flux q of component a at
+// node (start cell + o).
+template <typename R, typename Add>
+__device__ inline void deposit_move(const R d[3], const R D[3], R scale, Add &&add)
+{
+    R x1[3], lam[3], l0;
+    int dir[3], o0;
+    const int meta = move_order(d, D, 1, x1, dir, lam, o0, l0);
+    const int nb = (meta >> 2) & 3;
+    R p1[3];
+    if (nb == 0) {
+        p1[0] = x1[0]; p1[1] = x1[1]; p1[2] = x1[2];
+    } else {
+        crossing_point(d, D, dir, lam, o0, l0, p1);
+    }
+    const R dd[3] = {p1[0] - d[0], p1[1] - d[1], p1[2] - d[2]};
+    piece_fluxes(d, dd, scale, [&](int a, int f, auto q) {
+        const int b1 = a == 2 ? 0 : a + 1, b2 = a == 0 ? 2 : a - 1;
+        int o[3] = {0, 0, 0};
+        if (f & 1) o[b2] += 1;
+        if (f & 2) o[b1] += 1;
+        add(a, o[0], o[1], o[2], q);
+    });
+    if (nb > 0) deposit_chain(p1, x1, meta, 1, scale, add);
+}
+
+// The whole move d -> d + D as one chain from its start (the mirrored rest of
+// a move through a conducting wall, queued from its first piece).
+template <typename R, typename Add>
+__device__ inline void deposit_rest(const R d[3], const R D[3], R scale, Add &&add)
+{
+    R x1[3], lam[3], l0;
+    int dir[3], o0;
+    const int meta = move_order(d, D, 0, x1, dir, lam, o0, l0);
+    deposit_chain(d, x1, meta, 0, scale, add);
 }
 
 // The Boris step, the non-finite check and the displacement D = dt u / gamma
@@ -722,7 +802,7 @@ __device__ void push_overflow(const BoxDev<R> &B, int kblk, const StepConst<R> &
                     R Q2[3] = {P2[0], P2[1], P2[2]};
                     int s2[3];
                     wall_rest_start(B.wall, Q2, s2);
-                    deposit_move(Q2, D2, scale, [&](int a, int ox, int oy, int oz, JT q) {
+                    deposit_rest(Q2, D2, scale, [&](int a, int ox, int oy, int oz, JT q) {
                         put_j(a, s2[0] + ox, s2[1] + oy, s2[2] + oz, q);
                     });
                 } else {
@@ -898,7 +978,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     R *qval = reinterpret_cast<R *>(qmem + 2 * kWaves * kQCap * sizeof(int32_t)) + wave * 6 * kQCap;
     int qhead = 0, qcount = 0;                    // wave-uniform
     const uint64_t lt = lanemask_lt();
-    auto put = [&](bool has, int32_t w, int32_t meta, const R d[3], const R D[3]) {
+    auto put = [&](bool has, int32_t w, int32_t meta, const R ps[3], const R x1[3]) {
         const uint64_t mh = __ballot(has);
         if (has) {
             const int pos = (qhead + qcount + (int)__popcll(mh & lt)) & (kQCap - 1);
@@ -906,8 +986,8 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             qmeta[pos] = meta;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                qval[a * kQCap + pos] = d[a];
-                qval[(3 + a) * kQCap + pos] = D[a];
+                qval[a * kQCap + pos] = ps[a];
+                qval[(3 + a) * kQCap + pos] = x1[a];
             }
         }
         qcount += (int)__popcll(mh);
@@ -920,13 +1000,13 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int nq = min(qcount, 64);
         int32_t w = 0, meta = 0;
-        R d[3] = {R(0), R(0), R(0)}, D[3] = {R(0), R(0), R(0)};
+        R ps[3] = {R(0), R(0), R(0)}, x1[3] = {R(0), R(0), R(0)};
         if (lane < nq) {
             const int e = (qhead + lane) & (kQCap - 1);
             w = qidx[e];
             meta = qmeta[e];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) { d[a] = qval[a * kQCap + e]; D[a] = qval[(3 + a) * kQCap + e]; }
+            for (int a = 0; a < 3; ++a) { ps[a] = qval[a * kQCap + e]; x1[a] = qval[(3 + a) * kQCap + e]; }
         }
         qhead = (qhead + nq) & (kQCap - 1);
         qcount -= nq;
@@ -935,16 +1015,9 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int k = meta & 3, nb = (meta >> 2) & 3;
         bool more = false;
+        R pe[3] = {x1[0], x1[1], x1[2]};
         if (lane < nq) {
-            R x1[3], lam[3];
-            int dir[3];
-            move_crossings(d, D, x1, dir, lam);
-            const int oa = (meta >> (2 + 2 * k)) & 3, ob = (meta >> (4 + 2 * k)) & 3;   // axes of crossings k, k+1
-            R ps[3], pe[3];
-            if (k == 0) { ps[0] = d[0]; ps[1] = d[1]; ps[2] = d[2]; }
-            else crossing_point(d, D, dir, lam, oa, sel3(oa, lam[0], lam[1], lam[2]), ps);
-            if (k < nb) crossing_point(d, D, dir, lam, ob, sel3(ob, lam[0], lam[1], lam[2]), pe);
-            else { pe[0] = x1[0]; pe[1] = x1[1]; pe[2] = x1[2]; }
+            if (k < nb) chain_point(ps, x1, meta, k, pe);
             int offc[3];
             R sv[3], dd[3];
             piece_frame(ps, pe, offc, sv, dd);
@@ -953,7 +1026,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             deposit_piece<R>(jl, cb, joff, sv, dd, sc);
             more = k < nb;
         }
-        put(more, w, meta + 1, d, D);
+        put(more, w, meta + 1, pe, x1);
     };
     for (int s = 0; s < C.nsp; ++s) {
         const SpeciesDev<R> &S = B.sp[s];
@@ -1109,7 +1182,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                     atomic_add_global(&J[a * B.nc + i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)], q);
                 });
             }
-            put(valid && inside && nb > 0, jb | sgnbit, 1 | (nb << 2) | (o0 << 4) | (o1 << 6) | (o2 << 8), d, D);
+            put(valid && inside && nb > 0, jb | sgnbit, move_meta(1, nb, o0, o1, o2, dir), p1, x1);
             while (qcount >= 64) drain();
             if (WALLS && B.wall >= 0 && __ballot(hitw)) {
                 // the mirrored rest of the moves that hit a wall: a whole move
@@ -1125,10 +1198,10 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                 if (m2 < m1) { R t = m1; m1 = m2; m2 = t; int q = q1; q1 = q2; q2 = q; }
                 if (m1 < m0) { R t = m0; m0 = m1; m1 = t; int q = q0; q0 = q1; q1 = q; }
                 const int jb2 = jb + s2[0] + __mul24(JX, s2[1]) + __mul24(JXY, s2[2]);
-                put(hitw && inside, jb2 | sgnbit, 0 | (nb2 << 2) | (q0 << 4) | (q1 << 6) | (q2 << 8), P2, D2);
+                put(hitw && inside, jb2 | sgnbit, move_meta(0, nb2, q0, q1, q2, db), P2, y1);
                 if (hitw && !inside) {
                     PIC_GLOBAL JT *J = B.J;
-                    deposit_move(P2, D2, scale, [&](int a, int ox, int oy, int oz, JT q) {
+                    deposit_rest(P2, D2, scale, [&](int a, int ox, int oy, int oz, JT q) {
                         if (q == JT(0)) return;
                         const int i = wrap_idx(ix + s2[0] + ox, B.n[0]), j = wrap_idx(iy + s2[1] + oy, B.n[1]),
                                   k = wrap_idx(iz + s2[2] + oz, B.n[2]);

@@ -781,6 +781,43 @@ def test_single_harris_sheet_between_walls(fp64, tol):
     s.close()
 
 
+@pytest.mark.parametrize("fp64,tol", [(False, 1e-5), (True, 1e-11)])
+def test_overflowing_particles_hit_a_wall(fp64, tol):
+    # particles packed into the last quarter of x stream into the wall at
+    # x = N with tight segments: many land in the overflow region and take
+    # the HBM path through the wall (reflection, two-piece deposit)
+    rng = np.random.default_rng(13)
+    dims, n = (16, 8, 8), 6000
+    from paper_1308_5892_amd import pic as P
+    s = P.Simulation([{"n": dims, "n_x": 10.0, "rho0": 16.0, "max_particles": [n, n], "walls": 1}], G.PAIR, 0.5,
+                     fp64=fp64, track_ids=True, headroom=1.05)
+    st = G.oracle_state(dims, 10.0, 16.0)
+    st.wall = 0
+    parts = []
+    for sp in range(2):
+        x = rng.uniform(0, 1, (n, 3)) * np.array([4.0, 8.0, 8.0]) + np.array([12.0, 0.0, 0.0])
+        u = 0.05 * rng.standard_normal((n, 3))
+        u[: n // 4, 0] += 2.0
+        parts.append((x, u))
+    G.start(s, st, parts, fp64=fp64)
+    seen = 0
+    for _ in range(12):
+        s.step(1)
+        st.step(1)
+        seen = max(seen, int(s.diag(0)["n_overflow"].sum()))
+    assert seen > 0
+    for sp in range(2):
+        x, u, _ = s.particles(0, sp)
+        assert len(x) == n
+        assert G.u_rel_err(u, st.u[st.species == sp], 1e-3).max() < tol
+        assert np.all((x[:, 0] >= 0) & (x[:, 0] < dims[0]))
+    e, _, _ = s.fields(0)
+    assert np.max(np.abs(e - st.e)) < (1e-12 if fp64 else 1e-5) * max(np.abs(st.e).max(), 1e-30) + 1e-14
+    d = s.diag(0)
+    assert d["flags"] == 0
+    s.close()
+
+
 # single moves through a wall, some crossing other cell planes before or
 # after the wall: the current of each against the oracle's after one step
 _WALL_MOVES = [

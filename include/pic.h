@@ -242,7 +242,11 @@ int pic_set_particles(pic_ctx *ctx, int box, int species, const double *x, const
 /* Copy e^t, b^{t-dt/2} and the pending current (NULLs allowed) to the host. */
 int pic_get_fields(pic_ctx *ctx, int box, double *e, double *b, double *j);
 
-/* Set e^t and b^{t-dt/2} of a box (NULL leaves that field unchanged). */
+/*
+ * Set e^t and b^{t-dt/2} of a box (NULL leaves that field unchanged).  In a
+ * box with walls the tangential e and the normal b on the wall plane are set
+ * to zero, the conductor's condition (App. A.4).
+ */
 int pic_set_fields(pic_ctx *ctx, int box, const double *e, const double *b);
 
 /* Kernel timing of pic_step, from HIP events recorded on the context's stream

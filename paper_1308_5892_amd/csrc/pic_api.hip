@@ -842,13 +842,23 @@ static int set_fields_t(pic_ctx *ctx, int box, const double *e, const double *b)
     const BoxDev<R> &D = bdvec<R>(ctx)[box];
     const size_t n3 = 3 * D.nc;
     std::vector<R> tmp(n3);
+    // with conducting walls the given fields take the conductor's condition on
+    // the wall plane (index 0 along the wall axis): no tangential e, no
+    // normal b (App. A.4)
+    auto on_wall = [&](size_t p) {
+        const int64_t i = (int64_t)(p % D.n[0]), j = (int64_t)((p / D.n[0]) % D.n[1]),
+                      k = (int64_t)(p / ((size_t)D.n[0] * D.n[1]));
+        return D.wall >= 0 && (D.wall == 0 ? i : (D.wall == 1 ? j : k)) == 0;
+    };
     if (e) {
-        for (size_t q = 0; q < n3; ++q) tmp[q] = (R)e[q];
+        for (size_t q = 0; q < n3; ++q)
+            tmp[q] = ((int)(q / D.nc) != D.wall && on_wall(q % D.nc)) ? R(0) : (R)e[q];
         HIPCHK(hipMemcpyAsync(D.e, tmp.data(), n3 * sizeof(R), hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }
     if (b) {
-        for (size_t q = 0; q < n3; ++q) tmp[q] = (R)b[q];
+        for (size_t q = 0; q < n3; ++q)
+            tmp[q] = ((int)(q / D.nc) == D.wall && on_wall(q % D.nc)) ? R(0) : (R)b[q];
         HIPCHK(hipMemcpyAsync(D.b, tmp.data(), n3 * sizeof(R), hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }

@@ -400,19 +400,26 @@ def test_harris_field_and_backward_half_step():
     s.close()
 
 
-def test_multiple_boxes_in_one_launch():
+@pytest.mark.parametrize("walls", [(0, 0, 0), (0, 2, 3)], ids=["periodic", "mixed_walls"])
+def test_multiple_boxes_in_one_launch(walls):
+    # three boxes of different shapes in one launch; in the second case the
+    # middle box has walls across y and the last across z, next to a
+    # periodic box, so one launch runs both kinds of box
     from paper_1308_5892_amd import pic as P
     from oracle import oracle as O
     rng = np.random.default_rng(21)
     dims_list = [(8, 8, 8), (13, 6, 5), (4, 4, 12)]
     boxes, n = [], 500
-    for d in dims_list:
-        boxes.append({"n": d, "n_x": 10.0, "rho0": 8.0, "max_particles": [n, n]})
+    for d, w in zip(dims_list, walls):
+        boxes.append({"n": d, "n_x": 10.0, "rho0": 8.0, "max_particles": [n, n], "walls": w})
     sim = P.Simulation(boxes, G.PAIR, 0.5, fp64=True, track_ids=True)
     states = []
     for bi, d in enumerate(dims_list):
         e, b = G.random_fields(rng, int(np.prod(d)), 0.02, 0.2)
         st = O.State(d, 0.5, 10.0, 8.0, G.PAIR)
+        st.wall = walls[bi] - 1
+        if st.wall >= 0:
+            e, b = O.wall_fields(d, st.wall, e, b)   # start from fields that meet the walls' condition
         G.start(sim, st, [_random_particles(rng, d, n) for _ in range(2)], box=bi, e=e, b=b, fp64=True)
         states.append(st)
     sim.step(4)

@@ -399,21 +399,15 @@ __device__ inline int div_small(int q, int mul) { return (int)(__umul24((unsigne
 // v wrapped into [0, n) for v in [-n, 2n) (one correction step)
 __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// The twelve face values of one piece (App. A.3.4, eq. current_dep), added to
-// the tile current at jl[cb + off[a][f]]: component a, faces (pp, qq) in
-// {(0,0), (0,1), (1,0), (1,1)} along the two other axes b1 = a+1, b2 = a+2.
-// With m = s + dd/2 and K = dd_b1 dd_b2 / 12 the weights are
-// (1-m1)(1-m2)+K, (1-m1)m2-K, m1(1-m2)-K, m1 m2+K; they sum to one, so the
-// (0,0) value is the total minus the other three (taken after rounding to the
-// fixed-point grid in the FP32 form, so each component's four values add up
-// to the rounded total).
 // The twelve fluxes of one piece (start offset s in its cell, displacement
-// dd), eq. current_dep with the sign and scale of the species, rounded to the
-// fixed-point current: per component a, the four faces around the cell's
-// a-edge, f = 0 at the cell, 1 one step along b2, 2 one step along b1, 3 both
-// (b1, b2 the two other axes in cyclic order).  The four rounded values of a
-// component add up to the rounded total flux, so a piece moves exactly its
-// charge.  add(a, f, q) receives each rounded value.
+// dd), eq. current_dep (App. A.3.4) with the sign and scale of the species,
+// rounded to the fixed-point current: per component a, the four faces around
+// the cell's a-edge, f = 0 at the cell, 1 one step along b2, 2 one step along
+// b1, 3 both (b1, b2 the two other axes in cyclic order).  With
+// m = s + dd/2 and K = dd_b1 dd_b2 / 12 the weights are (1-m1)(1-m2)+K,
+// (1-m1)m2-K, m1(1-m2)-K and m1 m2+K; they sum to one, so the f = 0 value is
+// the rounded total minus the other three rounded values, and a piece moves
+// exactly its charge.  add(a, f, q) receives each rounded value.
 template <typename R, typename Add>
 __device__ inline void piece_fluxes(const R s[3], const R dd[3], R scale, Add &&add)
 {
@@ -433,6 +427,7 @@ __device__ inline void piece_fluxes(const R s[3], const R dd[3], R scale, Add &&
     }
 }
 
+// The fluxes of one piece added to the LDS tile current at jl[cb + off[a][f]].
 template <typename R>
 __device__ inline void deposit_piece(typename JType<R>::T *jl, int cb, const int (&off)[3][4], const R s[3],
                                      const R dd[3], R scale)
@@ -666,9 +661,9 @@ __device__ inline void deposit_rest(const R d[3], const R D[3], R scale, Add &&a
 
 // The Boris step, the non-finite check and the displacement D = dt u / gamma
 // of the move, shared by the tile and HBM paths.  D stays the rounded product
-// (opaque to the compiler, so that no multiply-add fuses it into d + D): a
-// queued move's crossings are recomputed from the stored (d, D) and must come
-// out identical.
+// (opaque to the compiler, so that no multiply-add fuses it into d + D): the
+// move's end x1 = d + D and its crossings must come out identical wherever
+// they are computed.
 template <typename R>
 __device__ inline void boris_move(R hk, const R E[3], const R Bf[3], R u[3], R dt, bool valid,
                                   PIC_GLOBAL uint32_t *flags, R D[3])
@@ -970,8 +965,8 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         }
     }
     // this wave's queue of unfinished moves: home-cell index (sign bit =
-    // species sign), meta = next piece | pieces << 2 | crossing order << 4,
-    // start offsets d and displacement D
+    // species sign), meta word (move_meta), start of the next piece and end
+    // of the move
     const int wave = tid >> 6, lane = __lane_id();
     int32_t *qidx = reinterpret_cast<int32_t *>(qmem) + wave * kQCap;
     int32_t *qmeta = reinterpret_cast<int32_t *>(qmem) + (kWaves + wave) * kQCap;

@@ -342,6 +342,39 @@ def test_largest_box_edges(dims, fp64, tol):
     s.close()
 
 
+@pytest.mark.parametrize("fp64,tol", [(False, 1e-5), (True, 1e-11)])
+@pytest.mark.parametrize("species", [[(-1.0, 1.0)], [(-1.0, 1.0), (1.0, 1.0), (1.0, 25.0), (-1.0, 4.0)]],
+                         ids=["one_species", "four_species"])
+def test_one_and_four_species(species, fp64, tol):
+    # the fewest and the most species a context takes, each with its own
+    # random particles (not co-located, so the fields build up), 10 steps;
+    # momenta, fields and the per-species diagnostics with a gamma-1
+    # histogram against the oracle
+    from paper_1308_5892_amd import pic as P
+    rng = np.random.default_rng(29)
+    dims, n, nbins = (10, 9, 8), 700, 24
+    s = P.Simulation([{"n": dims, "n_x": 10.0, "rho0": 8.0, "max_particles": [n] * len(species)}], species, 0.5,
+                     fp64=fp64, track_ids=True, hist_bins=nbins, hist_lo=-4.0, hist_hi=2.0)
+    st = G.oracle_state(dims, 10.0, 8.0, species=species)
+    G.start(s, st, [_random_particles(rng, dims, n) for _ in species], fp64=fp64)
+    s.step(10)
+    st.step(10)
+    for sp in range(len(species)):
+        x, u, _ = s.particles(0, sp)
+        assert G.u_rel_err(u, st.u[st.species == sp], 1e-2).max() < tol, sp
+        assert np.abs(G.wrap_delta(x, st.x[st.species == sp], dims)).max() < 100 * tol
+    e, b, _ = s.fields(0)
+    assert np.abs(e - st.e).max() < (1e-11 if fp64 else 1e-4) * np.abs(st.e).max()
+    d, r = s.diag(0, hist_bins=nbins), st.diag(nbins, -4.0, 2.0)
+    assert d["flags"] == 0
+    assert np.allclose(d["K"], r["K"], rtol=1e-10 if fp64 else 1e-5)
+    assert np.allclose(d["P"], r["P"], rtol=0, atol=(1e-10 if fp64 else 1e-5) * n)   # |u| ~ 1 per particle
+    assert d["count"].tolist() == [n] * len(species)
+    # histogram bins agree up to particles that sit on a bin edge within roundoff
+    assert np.abs(d["hist"] - r["hist"]).sum() <= (0 if fp64 else 4), (d["hist"], r["hist"])
+    s.close()
+
+
 def test_empty_plasma_and_zero_steps():
     s = G.sim((8, 8, 8), 10.0, 2.0, [0, 0])
     s.step(0)

@@ -375,6 +375,36 @@ def test_one_and_four_species(species, fp64, tol):
     s.close()
 
 
+@pytest.mark.parametrize("fp64", [False, True])
+def test_nonfinite_momentum_is_flagged_and_contained(fp64):
+    # a NaN and an oversized momentum given from the host: the push flags
+    # them (PIC_FLAG_NONFINITE, reported once as PIC_EFLAG by pic_diag), puts
+    # those two particles at rest and goes on; every momentum stays finite
+    # and no particle is lost
+    import ctypes as C
+    from paper_1308_5892_amd import pic as P
+    rng = np.random.default_rng(31)
+    dims, n = (8, 8, 8), 512
+    s = G.sim(dims, 10.0, 8.0, [n, n], fp64=fp64)
+    st = G.oracle_state(dims, 10.0, 8.0)           # only to share the storage rounding of the start
+    parts = [_random_particles(rng, dims, n) for _ in range(2)]
+    G.start(s, st, parts, fp64=fp64)
+    x0, u0 = G.to_storage(parts[0][0], parts[0][1], dims, fp64)
+    bad = u0.copy()
+    bad[5] = [np.nan, 0.0, 0.0]
+    bad[7] = [1e20, 0.0, 0.0]
+    s.set_particles(0, 0, x0, bad, np.arange(n))
+    s.step(1)
+    out = P.pic_diag_out()
+    assert P.lib().pic_diag(s.ctx, 0, C.byref(out), None) == P.PIC_EFLAG
+    assert out.flags & P.PIC_FLAG_NONFINITE
+    assert P.lib().pic_diag(s.ctx, 0, C.byref(out), None) == P.PIC_OK     # reported once
+    _, u, _ = s.particles(0, 0)
+    assert np.all(np.isfinite(u)) and np.abs(u[[5, 7]]).max() < 1e-3
+    assert s.diag(0)["count"].tolist() == [n, n]
+    s.close()
+
+
 def test_empty_plasma_and_zero_steps():
     s = G.sim((8, 8, 8), 10.0, 2.0, [0, 0])
     s.step(0)

@@ -166,7 +166,11 @@ __device__ inline void gather_global(const BoxDev<R> &B, int ix, int iy, int iz,
 
 // ------------------------------------------------------------ slot claims
 
-__device__ inline uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+// Number of lanes below this one whose bit is set in the wave mask m.
+__device__ inline int lane_rank(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
 
 // Wave-aggregated claim of one slot per pending lane in the counter of its
 // target segment: one atomic per distinct target in the wave.
@@ -183,7 +187,7 @@ __device__ inline int claim_slot(PIC_GLOBAL int32_t *cnt, int target, bool pendi
         if (__lane_id() == leader) base = atomicAdd(&cnt[tgt], (int)__popcll(mm));
         base = __shfl(base, leader);
         if (mine) {
-            slot = base + (int)__popcll(mm & lanemask_lt());
+            slot = base + lane_rank(mm);
             pending = false;
         }
     }
@@ -447,7 +451,7 @@ __device__ inline void move_crossings(const R d[3], const R D[3], R x1[3], int d
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         x1[a] = d[a] + D[a];
-        dir[a] = x1[a] < R(0) ? -1 : (x1[a] >= R(1) ? 1 : 0);
+        dir[a] = (int)floor(x1[a]);       // -1, 0 or 1, since x1 lies in (-1, 2)
         lam[a] = dir[a] != 0 ? ((dir[a] > 0 ? R(1) : R(0)) - d[a]) * fast_rcp(D[a]) : R(2);
     }
 }
@@ -507,12 +511,17 @@ template <typename R>
 __device__ inline void crossing_point(const R d[3], const R D[3], const int dir[3], const R lam[3], int ax, R l,
                                       R q[3])
 {
+    // branch-free: both clamps are formed and one is selected, so a wave
+    // whose lanes cross in different directions runs one straight sequence
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        R v = fma(l, D[a], d[a]);
-        if (dir[a] > 0) v = lam[a] <= l ? fmax(v, R(1)) : fmin(v, R(1));
-        else if (dir[a] < 0) v = lam[a] <= l ? fmin(v, R(0)) : fmax(v, R(0));
-        q[a] = a == ax ? (dir[a] > 0 ? R(1) : R(0)) : v;
+        const R v = fma(l, D[a], d[a]);
+        const R pl = dir[a] > 0 ? R(1) : R(0);
+        // the side of the plane to keep: above it (max) when the axis moves
+        // up and is crossed, or moves down and is not crossed yet
+        const bool above = (dir[a] > 0) == (lam[a] <= l);
+        const R c = above ? fmax(v, pl) : fmin(v, pl);
+        q[a] = a == ax ? pl : (dir[a] != 0 ? c : v);
     }
 }
 
@@ -549,10 +558,13 @@ __device__ inline void chain_point(const R ps[3], const R x1[3], int meta, int k
     for (int a = 0; a < 3; ++a) {
         const int da = ((meta >> (10 + 2 * a)) & 3) - 1;
         const bool far = (crossed >> a) & 1;
-        R v = fma(l, Dp[a], ps[a]);
-        if (da > 0) v = far ? fmax(v, R(1)) : fmin(v, R(1));
-        else if (da < 0) v = far ? fmin(v, R(0)) : fmax(v, R(0));
-        pe[a] = a == ax ? plane : v;
+        const R v = fma(l, Dp[a], ps[a]);
+        const R pl = da > 0 ? R(1) : R(0);
+        // branch-free, as in crossing_point: keep above the plane when the
+        // axis moves up and is crossed, or moves down and is not crossed yet
+        const bool above = (da > 0) == far;
+        const R c = above ? fmax(v, pl) : fmin(v, pl);
+        pe[a] = a == ax ? plane : (da != 0 ? c : v);
     }
 }
 
@@ -671,10 +683,13 @@ __device__ inline void boris_move(R hk, const R E[3], const R Bf[3], R u[3], R d
     boris(hk, E, Bf, u);
     // one test catches NaN and infinity (and |u| beyond 1e15)
     R u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    if (!(u2 < R(1e30))) {
-        if (valid) atomicOr(flags, PIC_FLAG_NONFINITE);
-        u[0] = u[1] = u[2] = R(0);
-        u2 = R(0);
+    const bool bad = !(u2 < R(1e30));
+    if (__builtin_expect(__ballot(bad) != 0, 0)) {     // wave-uniform: the fix-up costs nothing otherwise
+        if (bad) {
+            if (valid) atomicOr(flags, PIC_FLAG_NONFINITE);
+            u[0] = u[1] = u[2] = R(0);
+            u2 = R(0);
+        }
     }
     const R ig = dt * fast_rsqrt(R(1) + u2);
 #pragma unroll
@@ -832,6 +847,21 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     const int tid = threadIdx.x;
     const TileGeom<R> g = tile_geom<R, FIX>(B, T);
     const TileRim rim = tile_rim(B, g);
+    // per axis: box edge length, whether the tile touches the box edge (only
+    // then can a move wrap), and whether one tile spans the box
+    int bn[3];
+    bool edge[3], span[3];
+    bool fastbin = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bn[a] = B.n[a];
+        edge[a] = g.o[a] == 0 || g.o[a] + g.ext[a] >= bn[a];
+        span[a] = B.ntile[a] == 1;
+        // with two tiles along an axis the cells on both sides of a tile are
+        // the same cells, and a partial tile at the box's far end has its
+        // own extent: move_bin's rule decides there
+        fastbin &= B.ntile[a] != 2 && g.ext[a] == 4;
+    }
     // LDS: per-cell trilinear coefficients | piece queues | union of {raw e,
     // raw b, node fields} (set-up) and the tile current (particle loop)
     const int tsx = FIX ? 2 : B.tshift[0], tsxy = FIX ? 4 : B.tshift[0] + B.tshift[1];
@@ -972,11 +1002,10 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     int32_t *qmeta = reinterpret_cast<int32_t *>(qmem) + (kWaves + wave) * kQCap;
     R *qval = reinterpret_cast<R *>(qmem + 2 * kWaves * kQCap * sizeof(int32_t)) + wave * 6 * kQCap;
     int qhead = 0, qcount = 0;                    // wave-uniform
-    const uint64_t lt = lanemask_lt();
     auto put = [&](bool has, int32_t w, int32_t meta, const R ps[3], const R x1[3]) {
         const uint64_t mh = __ballot(has);
         if (has) {
-            const int pos = (qhead + qcount + (int)__popcll(mh & lt)) & (kQCap - 1);
+            const int pos = (qhead + qcount + lane_rank(mh)) & (kQCap - 1);
             qidx[pos] = w;
             qmeta[pos] = meta;
 #pragma unroll
@@ -1065,7 +1094,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             if (!inside) {
                 gather_global(B, ix, iy, iz, d, hdt, E, Bf);
             } else {
-                const R *cf = coef + kCoef * (lx | (ly << tsx) | (lz << tsxy));
+                const R *cf = coef + __umul24(kCoef, lx | (ly << tsx) | (lz << tsxy));
                 const R pxy = d[0] * d[1], pyz = d[1] * d[2], pzx = d[2] * d[0], pxyz = pxy * d[2];
                 R F[6];
 #pragma unroll
@@ -1101,7 +1130,10 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             // the stayers' block of slots by one returning atomic of their
             // lowest lane, each leaver its own; neither is waited for until
             // the deposit below is done
-            int cn[3] = {ix, iy, iz};
+            // (the periodic wrap only where a lane may cross the box edge: in
+            // a tile on the edge, or when a lane came from outside its tile)
+            const bool anyout = __ballot(valid && !inside) != 0;
+            int cn[3] = {ix, iy, iz}, lc[3] = {lx, ly, lz};
             R dn[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -1112,8 +1144,9 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                     f += 1;
                 }
                 dn[a] = v;
+                lc[a] += f;
                 int ci = cn[a] + f;
-                ci = ci < 0 ? ci + B.n[a] : (ci >= B.n[a] ? ci - B.n[a] : ci);
+                if (edge[a] || anyout) ci = ci < 0 ? ci + bn[a] : (ci >= bn[a] ? ci - bn[a] : ci);
                 cn[a] = ci;
             }
             const int32_t ncell = pack_cell(cn[0], cn[1], cn[2]);
@@ -1122,7 +1155,20 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             // tile's new A range, leavers into an adjacent tile are staged from
             // the back (both claimed with one LDS atomic per wave); anything
             // else claims its target's B range with a global atomic
-            const int bin = valid ? move_bin(g, rim, cn) : -1;
+            int bin;
+            if (FIX && fastbin && !anyout) {
+                // every valid lane started in this full 4x4x4 tile and moved at
+                // most one cell per axis: its direction code from the local
+                // cell, (lc + 4) >> 2 = 0, 1, 2 for lc = -1, 0..3, 4, and 1 on
+                // an axis that one tile spans (it wraps into the same tile);
+                // the same code as move_bin's
+                int code = 0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) code += ((span[a] ? 4 : lc[a] + 4) >> 2) * (a == 0 ? 1 : (a == 1 ? 3 : 9));
+                bin = valid ? code : -1;
+            } else {
+                bin = valid ? move_bin(g, rim, cn) : -1;
+            }
             const bool stay = bin == 13, lv = bin >= 0 && bin != 13;
             const uint64_t ms = __ballot(stay), ml = __ballot(lv);
             const int sl = ms ? __ffsll((unsigned long long)ms) - 1 : 0;
@@ -1135,9 +1181,9 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             bb = __builtin_amdgcn_readlane(bb, ll);
             int at = -1;
             if (stay) {
-                at = dst_start + fb + (int)__popcll(ms & lt);
+                at = dst_start + fb + lane_rank(ms);
             } else if (lv) {
-                at = dst_start + n - 1 - (bb + (int)__popcll(ml & lt));
+                at = dst_start + n - 1 - (bb + lane_rank(ml));
             } else if (valid) {
                 const int slot = atomicAdd(&S.nb[dst][tn], 1);
                 at = b_range_slot(B, S, dst, tn, S.bs[dst][tn] + slot, C.flags);

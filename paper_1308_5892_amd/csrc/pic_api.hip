@@ -361,8 +361,12 @@ static int init_t(pic_ctx *ctx)
     HIPCHK(hipMemsetAsync(ctx->arena, 0, ctx->L.bytes - 256, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->L.boxes, bd.data(), bd.size() * sizeof(BoxDev<R>), hipMemcpyHostToDevice, ctx->stream));
     // work items: per box its tiles then its overflow sweeps (box order), and
-    // the same list permuted so that consecutive tiles land on one XCD
-    // (blocks are dealt round-robin over the 8 XCDs of the MI355X)
+    // the push order: the tiles of all boxes permuted so that consecutive
+    // tiles land on one XCD (blocks are dealt round-robin over the 8 XCDs of
+    // the MI355X) and every XCD gets the same number of tiles, then the
+    // overflow sweeps.  Sweeps among the tiles would shift the XCD chunks:
+    // with 4096 tiles, 7 XCDs would get 514, two more than 4 full rounds of
+    // their 128 block slots, and those two would run alone at the end.
     std::vector<Item> items;
     std::vector<CellBlock> cbs;
     for (int b = 0; b < ctx->cfg.n_boxes; ++b) {
@@ -375,23 +379,28 @@ static int init_t(pic_ctx *ctx)
     ctx->box_item_off.push_back((int)items.size());
     ctx->box_cblock_off.push_back((int)cbs.size());
     const int n = (int)items.size();
-    std::vector<Item> perm(n);
+    std::vector<Item> perm;
+    perm.reserve(n);
     {
+        std::vector<Item> tiles, sweeps;
+        for (const Item &it : items) (it.tile >= 0 ? tiles : sweeps).push_back(it);
+        const int nt = (int)tiles.size();
         const int X = 8;
-        const int per = (n + X - 1) / X;
+        const int per = (nt + X - 1) / X;
         int g = 0;
-        std::vector<int> used(n, 0);
-        for (int blk = 0; blk < n; ++blk) {
-            // block blk runs on XCD blk % 8; give that XCD the next item of its chunk
+        std::vector<int> used(nt, 0);
+        for (int blk = 0; blk < nt; ++blk) {
+            // block blk runs on XCD blk % 8; give that XCD the next tile of its chunk
             const int x = blk % X, slot = blk / X;
             int src = x * per + slot;
-            if (src >= n || used[src]) {   // ragged tail: first unused item
+            if (src >= nt || used[src]) {   // ragged tail: first unused tile
                 while (used[g]) ++g;
                 src = g;
             }
             used[src] = 1;
-            perm[blk] = items[src];
+            perm.push_back(tiles[src]);
         }
+        perm.insert(perm.end(), sweeps.begin(), sweeps.end());
     }
     HIPCHK(hipMemcpyAsync(ctx->L.items_box, items.data(), n * sizeof(Item), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->L.items_push, perm.data(), n * sizeof(Item), hipMemcpyHostToDevice, ctx->stream));

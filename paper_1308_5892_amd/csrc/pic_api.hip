@@ -557,15 +557,15 @@ static int step_t(pic_ctx *ctx, int n)
                               ctx->walls ? 1 : 0, ctx->stream));
         mark(ctx, 0, false);
         mark(ctx, 1, true);
+        // the b update's last block also takes the overflow watch of the copy
+        // just written
         HIPCHK(launch_fields<R>(boxes, ctx->L.cblocks, ctx->L.n_cblocks, (R)ctx->cfg.dt, ctx->cfg.n_species, C.filter,
-                                ctx->cur, ctx->stream));
+                                ctx->cur, ctx->cfg.n_boxes, ctx->L.flags + 8, ctx->stream));
         mark(ctx, 1, false);
         ctx->cur ^= 1;
         ctx->step += 1;
         {
             const int w = (int)(ctx->step % kWatch);
-            HIPCHK(launch_overflow_watch<R>(boxes, ctx->cfg.n_boxes, ctx->cfg.n_species, ctx->cur, ctx->L.flags + 8,
-                                            ctx->stream));
             HIPCHK(hipMemcpyAsync(ctx->watch_host + w, ctx->L.flags + 8, sizeof(uint32_t), hipMemcpyDeviceToHost,
                                   ctx->stream));
             HIPCHK(hipEventRecord(ctx->watch_ev[w], ctx->stream));

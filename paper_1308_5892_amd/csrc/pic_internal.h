@@ -176,7 +176,7 @@ hipError_t launch_push(const BoxDev<R> *boxes, const Item *items, int nitems, si
                        int fixed444, int walls, hipStream_t st);
 template <typename R>
 hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R dt, int nsp, int filter,
-                         int clear_copy, hipStream_t st);
+                         int clear_copy, int nboxes, uint32_t *watch, hipStream_t st);
 template <typename R>
 hipError_t launch_advance_b(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R h, hipStream_t st);
 template <typename R>
@@ -190,9 +190,6 @@ hipError_t launch_mj_table(double theta, double gamma_beta, double *cum, int M, 
 template <typename R> hipError_t launch_load_pairs(const BoxDev<R> *boxes, const LoadArgs &L, hipStream_t st);
 template <typename R>
 hipError_t launch_harris_field(const BoxDev<R> *boxes, int64_t nc, const pic_harris_field &H, hipStream_t st);
-template <typename R>
-hipError_t launch_overflow_watch(const BoxDev<R> *boxes, int nboxes, int nsp, int copy, uint32_t *out,
-                                 hipStream_t st);
 template <typename R>
 hipError_t launch_spectrum(const BoxDev<R> *boxes, int box, const int n[3], int f, int c, int an, R hdt,
                            double *scratch, double *ps, hipStream_t st);

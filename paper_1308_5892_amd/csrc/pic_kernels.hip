@@ -1319,12 +1319,41 @@ __device__ inline void next_layout(const BoxDev<R> &B, int nsp, int old, int t)
     }
 }
 
+// Overflow watch, by one whole block: fill of the fullest overflow region
+// after a push, over every box and species of copy `copy` (the one just
+// written), in thousandths of the smaller of its capacity and kOvfBlocks *
+// 1024 particles (the load its sweep blocks take in four rounds).
+template <typename R>
+__device__ void overflow_watch_block(const BoxDev<R> *__restrict__ boxes, int nboxes, int nsp, int copy,
+                                     uint32_t *__restrict__ out)
+{
+    __shared__ unsigned int best;
+
+    if (threadIdx.x == 0) best = 0;
+    __syncthreads();
+    unsigned int m = 0;
+    for (int b = threadIdx.x; b < nboxes; b += kBlock) {
+        const BoxDev<R> &B = boxes[b];
+        for (int s = 0; s < nsp; ++s) {
+            const SpeciesDev<R> &S = B.sp[s];
+            const long long c = S.nb[copy][B.ntiles];
+            const long long cap = min((long long)S.ovf_cap, (long long)kOvfBlocks * 1024);
+            const unsigned int f = (unsigned int)min(1000LL, c * 1000LL / max(1LL, cap));
+            m = max(m, f);
+        }
+    }
+    atomicMax(&best, m);
+    __syncthreads();
+    if (threadIdx.x == 0) *out = best;
+}
+
 // b <- b - h curl e (App. A.3.2); with old >= 0 also prepares the tile
-// descriptors of copy `old` for the next push.
+// descriptors of copy `old` for the next push, and with watch set takes the
+// overflow watch of copy old ^ 1 in its last block.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) advance_b_kernel(const BoxDev<R> *__restrict__ boxes,
                                                            const CellBlock *__restrict__ blocks, R h, int nsp,
-                                                           int old)
+                                                           int old, int nboxes, uint32_t *__restrict__ watch)
 {
     const CellBlock cb = blocks[blockIdx.x];
     const BoxDev<R> &B = boxes[cb.box];
@@ -1333,6 +1362,9 @@ __global__ void __launch_bounds__(kBlock) advance_b_kernel(const BoxDev<R> *__re
         if (p < B.ntiles) next_layout(B, nsp, old, (int)p);
         if (p == 0) next_layout(B, nsp, old, B.ntiles);
     }
+    // the last block also takes the overflow watch of the copy the push just
+    // wrote (saves a launch per step); the whole block reaches the barriers
+    if (watch && blockIdx.x == gridDim.x - 1) overflow_watch_block(boxes, nboxes, nsp, old ^ 1, watch);
     if (p >= B.nc) return;
     const int n0 = B.n[0], n1 = B.n[1], n2 = B.n[2];
     const int i = (int)(p % n0), j = (int)((p / n0) % n1), k = (int)(p / ((int64_t)n0 * n1));
@@ -1840,9 +1872,10 @@ hipError_t launch_push(const BoxDev<R> *boxes, const Item *items, int nitems, si
 
 template <typename R>
 hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R dt, int nsp, int filter,
-                         int clear_copy, hipStream_t st)
+                         int clear_copy, int nboxes, uint32_t *watch, hipStream_t st)
 {
-    hipLaunchKernelGGL(advance_b_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt, nsp, clear_copy);
+    hipLaunchKernelGGL(advance_b_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt, nsp, clear_copy,
+                       nboxes, watch);
     if (filter) {
         hipLaunchKernelGGL(advance_e_smoothed_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt);
         hipLaunchKernelGGL(clear_current_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks);
@@ -1855,7 +1888,8 @@ hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nb
 template <typename R>
 hipError_t launch_advance_b(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R h, hipStream_t st)
 {
-    hipLaunchKernelGGL(advance_b_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, h, 0, -1);
+    hipLaunchKernelGGL(advance_b_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, h, 0, -1, 0,
+                       (uint32_t *)nullptr);
     return hipGetLastError();
 }
 
@@ -1881,43 +1915,6 @@ hipError_t launch_diag(const BoxDev<R> *boxes, int box, int64_t nc, const Item *
     if (nitems) hipLaunchKernelGGL(diag_particles_kernel<R>, dim3(nitems), dim3(kBlock), 0, st, boxes, items, C);
     const int nb = (int)((nc + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(diag_fields_kernel<R>, dim3(nb), dim3(kBlock), 0, st, boxes, box, C.dt, C.filter);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------ overflow watch
-
-// Fill of the fullest overflow region after a push, over every box and
-// species of copy `copy` (the one just written), in thousandths of the smaller
-// of its capacity and kOvfBlocks * 1024 particles (the load its sweep blocks
-// take in four rounds).
-template <typename R>
-__global__ void __launch_bounds__(kBlock) overflow_watch_kernel(const BoxDev<R> *__restrict__ boxes, int nboxes,
-                                                                int nsp, int copy, uint32_t *__restrict__ out)
-{
-    __shared__ unsigned int best;
-    if (threadIdx.x == 0) best = 0;
-    __syncthreads();
-    unsigned int m = 0;
-    for (int b = threadIdx.x; b < nboxes; b += kBlock) {
-        const BoxDev<R> &B = boxes[b];
-        for (int s = 0; s < nsp; ++s) {
-            const SpeciesDev<R> &S = B.sp[s];
-            const long long c = S.nb[copy][B.ntiles];
-            const long long cap = min((long long)S.ovf_cap, (long long)kOvfBlocks * 1024);
-            const unsigned int f = (unsigned int)min(1000LL, c * 1000LL / max(1LL, cap));
-            m = max(m, f);
-        }
-    }
-    atomicMax(&best, m);
-    __syncthreads();
-    if (threadIdx.x == 0) *out = best;
-}
-
-template <typename R>
-hipError_t launch_overflow_watch(const BoxDev<R> *boxes, int nboxes, int nsp, int copy, uint32_t *out,
-                                 hipStream_t st)
-{
-    hipLaunchKernelGGL(overflow_watch_kernel<R>, dim3(1), dim3(kBlock), 0, st, boxes, nboxes, nsp, copy, out);
     return hipGetLastError();
 }
 
@@ -2038,16 +2035,15 @@ hipError_t launch_spectrum(const BoxDev<R> *boxes, int box, const int n[3], int 
     template size_t push_lds_bytes<R>(int, int, int);                                                         \
     template hipError_t launch_push<R>(const BoxDev<R> *, const Item *, int, size_t, const StepConst<R> &,   \
                                        int, int, hipStream_t);                                                \
-    template hipError_t launch_fields<R>(const BoxDev<R> *, const CellBlock *, int, R, int, int, int,          \
-                                         hipStream_t);                                                        \
+    template hipError_t launch_fields<R>(const BoxDev<R> *, const CellBlock *, int, R, int, int, int, int,     \
+                                         uint32_t *, hipStream_t);                                                        \
     template hipError_t launch_advance_b<R>(const BoxDev<R> *, const CellBlock *, int, R, hipStream_t);       \
     template hipError_t launch_repack<R>(const BoxDev<R> *, int, const Item *, int, const StageItem *, int,    \
                                          const StepConst<R> &, hipStream_t);                                  \
     template hipError_t launch_diag<R>(const BoxDev<R> *, int, int64_t, const Item *, int,                    \
                                        const StepConst<R> &, hipStream_t);                                    \
     template hipError_t launch_spectrum<R>(const BoxDev<R> *, int, const int[3], int, int, int, R, double *,   \
-                                           double *, hipStream_t);                                            \
-    template hipError_t launch_overflow_watch<R>(const BoxDev<R> *, int, int, int, uint32_t *, hipStream_t);
+                                           double *, hipStream_t);
 
 PIC_INSTANTIATE(float)
 PIC_INSTANTIATE(double)

@@ -361,12 +361,15 @@ static int init_t(pic_ctx *ctx)
     HIPCHK(hipMemsetAsync(ctx->arena, 0, ctx->L.bytes - 256, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->L.boxes, bd.data(), bd.size() * sizeof(BoxDev<R>), hipMemcpyHostToDevice, ctx->stream));
     // work items: per box its tiles then its overflow sweeps (box order), and
-    // the push order: the tiles of all boxes permuted so that consecutive
-    // tiles land on one XCD (blocks are dealt round-robin over the 8 XCDs of
-    // the MI355X) and every XCD gets the same number of tiles, then the
-    // overflow sweeps.  Sweeps among the tiles would shift the XCD chunks:
-    // with 4096 tiles, 7 XCDs would get 514, two more than 4 full rounds of
-    // their 128 block slots, and those two would run alone at the end.
+    // the push order: the overflow sweeps first (an empty one exits at once, a
+    // busy one overlaps the tiles instead of trailing them), then the tiles of
+    // all boxes permuted so that consecutive tiles land on one XCD (blocks are
+    // dealt round-robin over the 8 XCDs of the MI355X) and every XCD gets the
+    // same number of tiles.  Sweeps among the tiles would shift the XCD
+    // chunks: with 4096 tiles, 7 XCDs would get 514, two more than 4 full
+    // rounds of their 128 block slots, and those two would run alone at the
+    // end.  The sweeps come in a multiple of 8, so the tiles' XCDs are kept.
+    static_assert(kOvfBlocks % 8 == 0, "overflow sweeps must keep the tiles' XCD order");
     std::vector<Item> items;
     std::vector<CellBlock> cbs;
     for (int b = 0; b < ctx->cfg.n_boxes; ++b) {
@@ -382,8 +385,8 @@ static int init_t(pic_ctx *ctx)
     std::vector<Item> perm;
     perm.reserve(n);
     {
-        std::vector<Item> tiles, sweeps;
-        for (const Item &it : items) (it.tile >= 0 ? tiles : sweeps).push_back(it);
+        std::vector<Item> tiles;
+        for (const Item &it : items) (it.tile >= 0 ? tiles : perm).push_back(it);
         const int nt = (int)tiles.size();
         const int X = 8;
         const int per = (nt + X - 1) / X;
@@ -400,7 +403,6 @@ static int init_t(pic_ctx *ctx)
             used[src] = 1;
             perm.push_back(tiles[src]);
         }
-        perm.insert(perm.end(), sweeps.begin(), sweeps.end());
     }
     HIPCHK(hipMemcpyAsync(ctx->L.items_box, items.data(), n * sizeof(Item), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->L.items_push, perm.data(), n * sizeof(Item), hipMemcpyHostToDevice, ctx->stream));

@@ -361,15 +361,13 @@ static int init_t(pic_ctx *ctx)
     HIPCHK(hipMemsetAsync(ctx->arena, 0, ctx->L.bytes - 256, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->L.boxes, bd.data(), bd.size() * sizeof(BoxDev<R>), hipMemcpyHostToDevice, ctx->stream));
     // work items: per box its tiles then its overflow sweeps (box order), and
-    // the push order: the overflow sweeps first (an empty one exits at once, a
-    // busy one overlaps the tiles instead of trailing them), then the tiles of
-    // all boxes permuted so that consecutive tiles land on one XCD (blocks are
-    // dealt round-robin over the 8 XCDs of the MI355X) and every XCD gets the
-    // same number of tiles.  Sweeps among the tiles would shift the XCD
-    // chunks: with 4096 tiles, 7 XCDs would get 514, two more than 4 full
-    // rounds of their 128 block slots, and those two would run alone at the
-    // end.  The sweeps come in a multiple of 8, so the tiles' XCDs are kept.
-    static_assert(kOvfBlocks % 8 == 0, "overflow sweeps must keep the tiles' XCD order");
+    // the push order: the same list cut into 8 chunks of equal tile counts
+    // (a box's sweeps stay with its last tiles), dealt so that XCD x runs chunk
+    // x (blocks go round-robin over the 8 XCDs of the MI355X) and neighbouring
+    // tiles meet in one L2.  Chunks cut by item count instead would be shifted
+    // by the sweeps: with 4096 tiles, 7 XCDs would get 514, two more than 4
+    // full rounds of their 128 block slots, and those two would run alone at
+    // the end.
     std::vector<Item> items;
     std::vector<CellBlock> cbs;
     for (int b = 0; b < ctx->cfg.n_boxes; ++b) {
@@ -382,26 +380,33 @@ static int init_t(pic_ctx *ctx)
     ctx->box_item_off.push_back((int)items.size());
     ctx->box_cblock_off.push_back((int)cbs.size());
     const int n = (int)items.size();
-    std::vector<Item> perm;
-    perm.reserve(n);
+    std::vector<Item> perm(n);
     {
-        std::vector<Item> tiles;
-        for (const Item &it : items) (it.tile >= 0 ? tiles : perm).push_back(it);
-        const int nt = (int)tiles.size();
         const int X = 8;
+        int nt = 0;
+        for (const Item &it : items) nt += it.tile >= 0;
         const int per = (nt + X - 1) / X;
+        // chunk x: items [cut[x], cut[x + 1])
+        std::vector<int> cut(X + 1, n);
+        cut[0] = 0;
+        for (int i = 0, tiles = 0, x = 1; i < n && x < X; ++i) {
+            if (items[i].tile >= 0 && ++tiles == per * x) cut[x++] = i + 1;
+        }
+        std::vector<int> next(cut.begin(), cut.end() - 1);
+        std::vector<int> used(n, 0);
         int g = 0;
-        std::vector<int> used(nt, 0);
-        for (int blk = 0; blk < nt; ++blk) {
-            // block blk runs on XCD blk % 8; give that XCD the next tile of its chunk
-            const int x = blk % X, slot = blk / X;
-            int src = x * per + slot;
-            if (src >= nt || used[src]) {   // ragged tail: first unused tile
+        for (int blk = 0; blk < n; ++blk) {
+            // block blk runs on XCD blk % 8: the next item of that chunk, or
+            // (chunk done) the first item not yet dealt
+            const int x = blk % X;
+            while (next[x] < cut[x + 1] && used[next[x]]) ++next[x];
+            int src = next[x] < cut[x + 1] ? next[x]++ : -1;
+            if (src < 0) {
                 while (used[g]) ++g;
                 src = g;
             }
             used[src] = 1;
-            perm.push_back(tiles[src]);
+            perm[blk] = items[src];
         }
     }
     HIPCHK(hipMemcpyAsync(ctx->L.items_box, items.data(), n * sizeof(Item), hipMemcpyHostToDevice, ctx->stream));

@@ -42,9 +42,11 @@ def _random_particles(rng, dims, n):
 
 
 @pytest.mark.parametrize("fp64", [False, True])
-def test_one_step_on_frozen_fields(fp64):
+@pytest.mark.parametrize("dims", [(9, 8, 6), (12, 12, 12), (4, 12, 12)])
+def test_one_step_on_frozen_fields(fp64, dims):
+    # ragged tiles; full 4x4x4 tiles, 3 per axis; one tile spanning x: the
+    # re-binning takes its general and its full-tile form
     rng = np.random.default_rng(42)
-    dims = (9, 8, 6)
     n = 3000
     s = G.sim(dims, 10.0, 40.0, [n, n], fp64=fp64)
     st = G.oracle_state(dims, 10.0, 40.0)

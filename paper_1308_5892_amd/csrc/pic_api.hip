@@ -243,7 +243,8 @@ struct pic_ctx {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
     std::vector<hipEvent_t> ev_pool;
-    uint32_t *watch_host = nullptr;          // pinned, kWatch slots
+    uint32_t *watch_host = nullptr;          // pinned, coherent, kWatch slots
+    uint32_t *watch_dev = nullptr;           // the same slots as the device addresses them
     hipEvent_t watch_ev[kWatch] = {};
     int64_t watch_step[kWatch] = {-1, -1, -1, -1};
     int64_t last_repack = 0;
@@ -475,8 +476,16 @@ int pic_init(const pic_config *cfg, void *dev_arena, size_t bytes, void *hip_str
     ctx->stage_n.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
     ctx->stage_half.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
     ctx->next_id.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
-    if (hipHostMalloc(reinterpret_cast<void **>(&ctx->watch_host), kWatch * sizeof(uint32_t)) != hipSuccess) {
+    // the b update writes the watch straight into these slots (coherent, so
+    // the host reads it once the step's event has completed): no copy per step
+    if (hipHostMalloc(reinterpret_cast<void **>(&ctx->watch_host), kWatch * sizeof(uint32_t),
+                      hipHostMallocCoherent) != hipSuccess) {
         ctx->watch_host = nullptr;
+        delete ctx;
+        return PIC_EDEVICE;
+    }
+    for (int i = 0; i < kWatch; ++i) ctx->watch_host[i] = 0;
+    if (hipHostGetDevicePointer(reinterpret_cast<void **>(&ctx->watch_dev), ctx->watch_host, 0) != hipSuccess) {
         delete ctx;
         return PIC_EDEVICE;
     }
@@ -565,19 +574,15 @@ static int step_t(pic_ctx *ctx, int n)
         mark(ctx, 0, false);
         mark(ctx, 1, true);
         // the b update's last block also takes the overflow watch of the copy
-        // just written
+        // just written, into the host slot of the step about to complete
+        const int w = (int)((ctx->step + 1) % kWatch);
         HIPCHK(launch_fields<R>(boxes, ctx->L.cblocks, ctx->L.n_cblocks, (R)ctx->cfg.dt, ctx->cfg.n_species, C.filter,
-                                ctx->cur, ctx->cfg.n_boxes, ctx->L.flags + 8, ctx->stream));
+                                ctx->cur, ctx->cfg.n_boxes, ctx->watch_dev + w, ctx->stream));
         mark(ctx, 1, false);
         ctx->cur ^= 1;
         ctx->step += 1;
-        {
-            const int w = (int)(ctx->step % kWatch);
-            HIPCHK(hipMemcpyAsync(ctx->watch_host + w, ctx->L.flags + 8, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                                  ctx->stream));
-            HIPCHK(hipEventRecord(ctx->watch_ev[w], ctx->stream));
-            ctx->watch_step[w] = ctx->step;
-        }
+        HIPCHK(hipEventRecord(ctx->watch_ev[w], ctx->stream));
+        ctx->watch_step[w] = ctx->step;
         if (ctx->cfg.sort_interval > 0 && ctx->step % ctx->cfg.sort_interval == 0) {
             mark(ctx, 2, true);
             int rc = merge_t<R>(ctx, true);

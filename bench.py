@@ -239,7 +239,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--tile", type=int, nargs=3, default=(4, 4, 4))
-    ap.add_argument("--sort-interval", type=int, default=50)
+    ap.add_argument("--sort-interval", type=int, default=200)
     ap.add_argument("--fp64-steps", type=int, default=40)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

@@ -303,7 +303,8 @@ typedef struct pic_tune_result {
  * method; the work split of this library).  Boxes are grouped by particle
  * capacity per cell (below 32, below 128, above); for each group in turn the
  * tile shapes 4x4x4, 8x4x4 and 8x8x4 are tried on the whole configuration,
- * keeping the fastest, then the sort interval among 25, 50, 100 and cfg's.
+ * keeping the fastest, then the sort interval among 25, 50, 100, 200 and
+ * cfg's.
  * Each trial creates a context in dev_arena (borrowed, 256-byte aligned,
  * `bytes` long; size it with pic_plan for cfg with its smallest tiles),
  * applies the n_loads loads, runs steps/2 warm-up and `steps` timed steps on

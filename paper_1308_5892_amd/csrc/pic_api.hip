@@ -1128,7 +1128,7 @@ int pic_autotune(const pic_config *cfg, const pic_load_desc *loads, int n_loads,
     }
     const int si_keep = c.sort_interval;
     int si_best = si_keep;
-    for (int si : {25, 50, 100}) {
+    for (int si : {25, 50, 100, 200}) {
         if (si == si_keep) continue;
         c.sort_interval = si;
         const double ms = tune_trial(&c, loads, n_loads, dev_arena, bytes, hip_stream, steps);

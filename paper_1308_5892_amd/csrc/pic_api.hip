@@ -209,9 +209,9 @@ static void make_layout(const pic_config *cfg, std::vector<BoxHost> &bh, char *b
 
 using namespace pic;
 
-// Overflow watch: after every step a one-block kernel writes the fill of the
-// fullest overflow region (thousandths of its capacity) to a device word that
-// is copied to pinned host memory; pic_step reads it kWatchLag steps later
+// Overflow watch: after every push the last block of the b update writes the
+// fill of the fullest overflow region (thousandths of its capacity) straight
+// into a slot of coherent pinned host memory; pic_step reads it kWatchLag steps later
 // (waiting for that step only, so the stream stays kWatchLag steps ahead) and
 // repacks at once when the fill is above kWatchLimit, instead of letting the
 // overflow region - swept by the slow path - fill up or lose particles.

@@ -287,6 +287,41 @@ def test_overflow_region_keeps_parity():
     s.close()
 
 
+def test_overflow_watch_repacks_early():
+    # no periodic repack: an eighth of the particles stream into tiles laid
+    # out empty, the overflow region (1024 particles per species) fills past
+    # half, and the overflow watch, written by the b update into host memory,
+    # has pic_step repack before the region runs out; nothing is lost and the
+    # run follows the oracle
+    from paper_1308_5892_amd import pic as P
+    rng = np.random.default_rng(12)
+    dims = (16, 8, 8)
+    n = 6000
+    s = G.sim(dims, 10.0, 16.0, [n, n], fp64=True, headroom=1.05, sort_interval=0)
+    st = G.oracle_state(dims, 10.0, 16.0)
+    parts = []
+    for sp in range(2):
+        x = rng.uniform(0, 1, (n, 3)) * np.array([4.0, 8.0, 8.0])
+        u = 0.05 * rng.standard_normal((n, 3))
+        u[: n // 8, 0] += 3.0
+        parts.append((x, u))
+    G.start(s, st, parts, fp64=True)
+    P.pic_set_timing(s.ctx, 1)
+    seen = 0
+    for _ in range(20):
+        s.step(1)
+        st.step(1)
+        seen = max(seen, int(s.diag(0)["n_overflow"].max()))
+    assert seen > 512, seen                  # the watch limit: half the region
+    assert P.pic_get_timing(s.ctx)["sort_launches"] >= 1
+    assert s.diag(0)["flags"] == 0
+    for sp in range(2):
+        x, u, _ = s.particles(0, sp)
+        assert len(x) == n
+        assert G.u_rel_err(u, st.u[st.species == sp], 1e-3).max() < 1e-11
+    s.close()
+
+
 @pytest.mark.parametrize("dims,tile", [((1, 1, 1), (4, 4, 4)), ((3, 2, 5), (2, 1, 8)), ((7, 9, 2), (8, 2, 1))])
 def test_tiny_and_odd_boxes(dims, tile):
     rng = np.random.default_rng(3)

@@ -199,7 +199,7 @@ def time_form(wl, fp64, steps, warmup, sort_interval):
 
 def cpu_baseline(w):
     """The FP64 oracle, single-threaded, on 32^3 cells at the workload's density
-    and temperature: pushes per second over 2 full steps."""
+    and temperature: pushes per second over 4 full steps (about 13 s)."""
     from oracle import oracle as O
     dims = (32, 32, 32)
     npairs = w["ppc"] * 32 ** 3
@@ -208,7 +208,7 @@ def cpu_baseline(w):
     st = O.State(dims, w["dt"], w["n_x"], 2.0 * w["ppc"], [(-1.0, 1.0), (1.0, 1.0)])
     st.add_particles(0, x, ua)
     st.add_particles(1, x, ub)
-    nsteps = 2
+    nsteps = 4
     t0 = time.perf_counter()
     st.step(nsteps)
     dt = time.perf_counter() - t0

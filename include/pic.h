@@ -202,10 +202,10 @@ int pic_set_harris_field(pic_ctx *ctx, const pic_harris_field *h);
  * every sort_interval steps, and also as soon as an overflow region (the
  * slow path for particles whose tile segment is full) is half full, or holds
  * more than 8192 particles:
- * after each step a small kernel reports the fullest one, and pic_step reads
- * that report two steps later, so it keeps the stream at most two steps ahead
- * of the host instead of returning at once.  Uses pinned host memory (a few
- * bytes) allocated by pic_init.  Which particles take the slow path depends
+ * after each push the b update writes the fill of the fullest one into
+ * coherent pinned host memory (a few bytes, allocated by pic_init), and
+ * pic_step reads that report two steps later, so it keeps the stream at most
+ * two steps ahead of the host instead of returning at once.  Which particles take the slow path depends
  * on the order of the slot claims, but it computes the same arithmetic as the
  * tile path, and the FP32 form sums the current in int64 fixed point: a run
  * of the FP32 form is bitwise reproducible.

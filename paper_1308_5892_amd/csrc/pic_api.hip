@@ -231,6 +231,7 @@ struct pic_ctx {
     std::vector<int> box_item_off;          // first item of each box in items_box
     std::vector<int> box_cblock_off;        // first cell block of each box
     std::vector<std::vector<int32_t>> stage_n, stage_half, next_id;
+    std::vector<std::vector<int64_t>> binned;   // particles binned per (box, species), for the capacity check
     int cur = 0;
     int64_t step = 0;
     size_t lds_bytes = 0;
@@ -343,6 +344,8 @@ static int merge_t(pic_ctx *ctx, bool force)
     HIPCHK(launch_repack<R>(reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes), ctx->cfg.n_boxes, ctx->L.items_box,
                             ctx->L.n_items, ctx->L.sitems, (int)si.size(), C, ctx->stream));
     ctx->cur ^= 1;
+    for (int b = 0; b < ctx->cfg.n_boxes; ++b)
+        for (int s = 0; s < ctx->cfg.n_species; ++s) ctx->binned[b][s] += ctx->stage_n[b][s];
     for (auto &v : ctx->stage_n) std::fill(v.begin(), v.end(), 0);
     ctx->pending = false;
     if (!si.empty()) HIPCHK(hipStreamSynchronize(ctx->stream));   // the host stage list must outlive the copy
@@ -474,6 +477,7 @@ int pic_init(const pic_config *cfg, void *dev_arena, size_t bytes, void *hip_str
     ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
     ctx->arena = reinterpret_cast<char *>(dev_arena);
     ctx->stage_n.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
+    ctx->binned.assign(cfg->n_boxes, std::vector<int64_t>(kMaxSpecies, 0));
     ctx->stage_half.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
     ctx->next_id.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
     // the b update writes the watch straight into these slots (coherent, so
@@ -769,6 +773,7 @@ static int set_particles_t(pic_ctx *ctx, int box, int s, const double *x, const 
     // drop the binned particles of (box, s): clear the counters of the current copy
     HIPCHK(hipMemsetAsync(S.na[ctx->cur], 0, (D.ntiles + 1) * sizeof(int32_t), ctx->stream));
     HIPCHK(hipMemsetAsync(S.nb[ctx->cur], 0, (D.ntiles + 1) * sizeof(int32_t), ctx->stream));
+    ctx->binned[box][s] = 0;
     std::vector<int32_t> cell(n), pid(S.stage.id ? n : 0);
     std::vector<R> dd[3], uu[3];
     for (int a = 0; a < 3; ++a) { dd[a].resize(n); uu[a].resize(n); }
@@ -908,8 +913,9 @@ static int load_t(pic_ctx *ctx, const pic_load_desc *d)
         npairs = std::llround(d->ppc * cross * 2.0 * d->thickness * std::tanh(d->half_width / d->thickness));
     }
     const int sa = d->species_a, sb = d->species_b;
-    const int64_t need_a = ctx->stage_n[box][sa] + npairs + (sa == sb ? npairs : 0);
-    const int64_t need_b = ctx->stage_n[box][sb] + npairs;
+    // particles already binned count against the capacity too
+    const int64_t need_a = ctx->binned[box][sa] + ctx->stage_n[box][sa] + npairs + (sa == sb ? npairs : 0);
+    const int64_t need_b = ctx->binned[box][sb] + ctx->stage_n[box][sb] + npairs;
     if (need_a > H.stage_cap[sa] || need_b > H.stage_cap[sb]) {
         ctx->err = "load exceeds the species capacity";
         return PIC_ENOMEM;

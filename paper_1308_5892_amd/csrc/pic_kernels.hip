@@ -1562,6 +1562,8 @@ __global__ void __launch_bounds__(kBlock) repack_layout_kernel(const BoxDev<R> *
     __syncthreads();
     const long long region = (long long)S.slots - S.ovf_cap;
     if (total > region) {                              // uniform: the whole block leaves
+        // the counts still start from zero at the next repack
+        for (int t = t0; t < t1; ++t) S.tcount[t] = 0;
         if (tid == 0) atomicOr((PIC_GLOBAL uint32_t *)flags, PIC_FLAG_LOST);
         return;
     }
@@ -1854,14 +1856,15 @@ template <typename R>
 hipError_t launch_push(const BoxDev<R> *boxes, const Item *items, int nitems, size_t lds, const StepConst<R> &C,
                        int fixed444, int walls, hipStream_t st)
 {
-    // dynamic LDS beyond 64 KiB has to be allowed per kernel, once
-    static bool raised[4] = {false, false, false, false};
+    // dynamic LDS beyond 64 KiB has to be allowed per kernel: the limit each
+    // variant was last raised to, raised again when a launch needs more
+    static size_t raised[4] = {65536, 65536, 65536, 65536};
     auto go = [&](auto kern, int v) -> hipError_t {
-        if (lds > 65536 && !raised[v]) {
+        if (lds > raised[v]) {
             const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
-            raised[v] = true;
+            raised[v] = lds;
         }
         hipLaunchKernelGGL(kern, dim3(nitems), dim3(kBlock), lds, st, boxes, items, C);
         return hipGetLastError();

@@ -33,3 +33,22 @@ def test_traffic_is_reported_for_the_measured_source_only(tmp_path, monkeypatch)
     assert bench.pmc_traffic("x") is None
     assert bench.pmc_traffic("missing") is None
 
+
+
+def test_benchmark_harris_sheet_follows_the_oracle_relations(orc):
+    # the benchmark sets up its double Harris sheet with its own copy of the
+    # App. C relations; they must give the oracle's equilibrium (the oracle's
+    # relations are pinned to Table 4 and to pressure balance)
+    import pic_inputs as W
+    cases = [dict(W.HARRIS), dict(W.HARRIS_SMALL),
+             dict(W.HARRIS, theta_e=0.1, gu_e=0.40, mass_ratio=1.0),
+             dict(W.HARRIS, theta_e=0.3, gu_e=0.5, chi=1.7, mass_ratio=49.0, n_x=7.0)]
+    for w in cases:
+        hb = bench.harris_parameters(w)
+        ho = orc.harris_params(w["theta_e"], w["gu_e"], w["chi"], w["mass_ratio"])
+        assert abs(hb["L"] - ho["L_over_de"] * w["n_x"]) < 1e-12 * hb["L"]
+        assert abs(hb["b0"] - ho["wce_over_wpe"] / w["n_x"]) < 1e-12 * hb["b0"]
+        assert abs(hb["theta_i"] - ho["theta_i"]) < 1e-15
+        # the ions drift against the electrons: the oracle gives the signed
+        # value, the benchmark the magnitude it loads with the opposite sign
+        assert abs(hb["gu_i"] + ho["gu_i"]) < 1e-15

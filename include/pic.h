@@ -222,6 +222,22 @@ int pic_step(pic_ctx *ctx, int n);
 int pic_diag(pic_ctx *ctx, int box, pic_diag_out *out, int64_t *hist);
 
 /*
+ * For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): pic_diag with the
+ * same arguments and results, whose accumulators, charge density and
+ * histogram live in a static device array of the library (32 MiB per GPU,
+ * held until the process ends; its device address is taken by pic_init)
+ * instead of the context's arena.  It calls no allocator, and clears what
+ * it sums with kernels (no memset).  The box may need at most 32 MiB:
+ * 8 bytes per cell plus about 2 KiB, so about 4.1 M cells; a larger box gives
+ * PIC_ENOMEM.  Particles loaded or set since the last pic_step / pic_diag are
+ * not binned by this call: it returns PIC_ESTATE then.  Every context on one
+ * GPU shares the array, so calls that overlap on one GPU (different
+ * streams or threads) race; calls on one stream are ordered.  Synchronises.
+ */
+int pic_diag_noalloc(pic_ctx *ctx, int box, pic_diag_out *out, int64_t *hist);
+
+/*
  * Copy particles of (box, species) to the host as FP64: x[3n] absolute
  * positions in [0, n_axis), u[3n], id[n] (NULL allowed; zeros without
  * PIC_TRACK_IDS).  *n: in = capacity of the arrays, out = particle count

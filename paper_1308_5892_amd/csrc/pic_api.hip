@@ -498,6 +498,11 @@ int pic_init(const pic_config *cfg, void *dev_arena, size_t bytes, void *hip_str
             delete ctx;
             return PIC_EDEVICE;
         }
+    // device address of pic_diag_noalloc's static scratch on this device (once per device)
+    if (diag_scratch_setup() != hipSuccess) {
+        delete ctx;
+        return PIC_EDEVICE;
+    }
     rc = ctx->fp64 ? init_t<double>(ctx) : init_t<float>(ctx);
     if (rc) {
         fprintf(stderr, "pic_init: %s\n", ctx->err.c_str());
@@ -606,23 +611,24 @@ int pic_step(pic_ctx *ctx, int n)
     return ctx->fp64 ? step_t<double>(ctx, n) : step_t<float>(ctx, n);
 }
 
+// The diagnostics summed into `buf` (the arena's buffers of the box, or the
+// static scratch of pic_diag_noalloc).  Allocates nothing: the histogram goes
+// straight into the caller's array.
 template <typename R>
-static int diag_t(pic_ctx *ctx, int box, pic_diag_out *o, int64_t *hist)
+static int diag_t(pic_ctx *ctx, int box, pic_diag_out *o, int64_t *hist, const DiagBuf &buf)
 {
     const BoxDev<R> *boxes = reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes);
     const BoxDev<R> &D = bdvec<R>(ctx)[box];
     const int nsp = ctx->cfg.n_species;
-    const int hb = std::max(1, ctx->cfg.hist_bins);
-    HIPCHK(hipMemsetAsync(D.acc, 0, kAccLen * sizeof(double), ctx->stream));
-    HIPCHK(hipMemsetAsync(D.rho, 0, D.nc * sizeof(double), ctx->stream));
-    HIPCHK(hipMemsetAsync(D.hist, 0, (size_t)hb * kMaxSpecies * sizeof(int64_t), ctx->stream));
+    const int hist_len = std::max(1, ctx->cfg.hist_bins) * kMaxSpecies;
     StepConst<R> C = step_const<R>(ctx);
     const int i0 = ctx->box_item_off[box], i1 = ctx->box_item_off[box + 1];
-    HIPCHK(launch_diag<R>(boxes, box, D.nc, ctx->L.items_box + i0, i1 - i0, C, ctx->stream));
+    HIPCHK(launch_diag<R>(boxes, box, D.nc, ctx->L.items_box + i0, i1 - i0, C, buf, hist_len, ctx->stream));
     double acc[kAccLen];
-    HIPCHK(hipMemcpyAsync(acc, D.acc, sizeof(acc), hipMemcpyDeviceToHost, ctx->stream));
-    std::vector<int64_t> hh((size_t)hb * kMaxSpecies);
-    HIPCHK(hipMemcpyAsync(hh.data(), D.hist, hh.size() * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(acc, buf.acc, sizeof(acc), hipMemcpyDeviceToHost, ctx->stream));
+    if (hist && ctx->cfg.hist_bins > 0)   // device layout [species][bins], as the caller's
+        HIPCHK(hipMemcpyAsync(hist, buf.hist, (size_t)nsp * ctx->cfg.hist_bins * sizeof(int64_t),
+                              hipMemcpyDeviceToHost, ctx->stream));
     int32_t novf[kMaxSpecies] = {0, 0, 0, 0};
     for (int s = 0; s < nsp; ++s)
         HIPCHK(hipMemcpyAsync(&novf[s], D.sp[s].nb[ctx->cur] + D.ntiles, sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -645,10 +651,6 @@ static int diag_t(pic_ctx *ctx, int box, pic_diag_out *o, int64_t *hist)
         o->sum_gm1[s] = a[5];
         o->n_overflow[s] = std::min(novf[s], D.sp[s].ovf_cap);
     }
-    if (hist && ctx->cfg.hist_bins > 0)
-        for (int s = 0; s < nsp; ++s)
-            memcpy(hist + (size_t)s * ctx->cfg.hist_bins, hh.data() + (size_t)s * ctx->cfg.hist_bins,
-                   ctx->cfg.hist_bins * sizeof(int64_t));
     uint32_t f = 0;
     int rc = read_flags(ctx, &f);
     if (rc) return rc;
@@ -667,7 +669,53 @@ int pic_diag(pic_ctx *ctx, int box, pic_diag_out *out, int64_t *hist)
     if (!out) return PIC_EINVAL;
     rc = merge(ctx);
     if (rc) return rc;
-    return ctx->fp64 ? diag_t<double>(ctx, box, out, hist) : diag_t<float>(ctx, box, out, hist);
+    if (ctx->fp64) {
+        const BoxDev<double> &D = bdvec<double>(ctx)[box];
+        return diag_t<double>(ctx, box, out, hist, DiagBuf{D.acc, D.rho, D.hist});
+    }
+    const BoxDev<float> &D = bdvec<float>(ctx)[box];
+    return diag_t<float>(ctx, box, out, hist, DiagBuf{D.acc, D.rho, D.hist});
+}
+
+// Bytes of the static scratch that pic_diag_noalloc needs for box `box`:
+// accumulators, charge density, histogram, each 256-B aligned.
+static size_t noalloc_diag_bytes(const pic_ctx *ctx, int box)
+{
+    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t hist_len = (size_t)std::max(1, ctx->cfg.hist_bins) * kMaxSpecies;
+    return up(kAccLen * sizeof(double)) + up((size_t)ctx->bh[box].nc * sizeof(double)) +
+           up(hist_len * sizeof(int64_t));
+}
+
+int pic_diag_noalloc(pic_ctx *ctx, int box, pic_diag_out *out, int64_t *hist)
+{
+    int rc = check_box(ctx, box);
+    if (rc) return rc;
+    if (!out) return PIC_EINVAL;
+    if (ctx->pending) {
+        // binning staged particles would copy a host-built list; pic_step or
+        // pic_diag bins them
+        ctx->err = "pic_diag_noalloc: loaded or set particles are not binned yet (call pic_step or pic_diag first)";
+        return PIC_ESTATE;
+    }
+    const size_t need = noalloc_diag_bytes(ctx, box);
+    if (need > kDiagScratchBytes) {
+        ctx->err = "pic_diag_noalloc: the box needs more than the static scratch holds (8 bytes per cell plus "
+                   "accumulators and histogram, at most 32 MiB)";
+        return PIC_ENOMEM;
+    }
+    char *p = reinterpret_cast<char *>(diag_scratch());
+    if (!p) {
+        ctx->err = "pic_diag_noalloc: the static scratch is not set up on the current device";
+        return PIC_EDEVICE;
+    }
+    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    DiagBuf buf;
+    buf.acc = reinterpret_cast<double *>(p);
+    buf.rho = reinterpret_cast<double *>(p + up(kAccLen * sizeof(double)));
+    buf.hist = reinterpret_cast<int64_t *>(p + up(kAccLen * sizeof(double)) +
+                                           up((size_t)ctx->bh[box].nc * sizeof(double)));
+    return ctx->fp64 ? diag_t<double>(ctx, box, out, hist, buf) : diag_t<float>(ctx, box, out, hist, buf);
 }
 
 template <typename R>

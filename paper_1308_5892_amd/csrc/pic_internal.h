@@ -169,6 +169,19 @@ struct LoadArgs {
     MJPop A, B;
 };
 
+// Where the diagnostics sum: kAccLen accumulators, the charge density (one
+// value per cell) and the gamma-1 histogram (n_species x bins).  pic_diag
+// points it into the arena, pic_diag_noalloc into the library's static
+// scratch.
+struct DiagBuf {
+    PIC_GLOBAL double *acc;
+    PIC_GLOBAL double *rho;
+    PIC_GLOBAL int64_t *hist;
+};
+
+// size of the static scratch of pic_diag_noalloc (per GPU)
+constexpr size_t kDiagScratchBytes = size_t(32) << 20;
+
 // launchers (pic_kernels.hip, pic_loader.hip)
 template <typename R> size_t push_lds_bytes(int t0, int t1, int t2);
 template <typename R>
@@ -184,7 +197,11 @@ hipError_t launch_repack(const BoxDev<R> *boxes, int nboxes, const Item *items, 
                          const StageItem *sitems, int nsitems, const StepConst<R> &C, hipStream_t st);
 template <typename R>
 hipError_t launch_diag(const BoxDev<R> *boxes, int box, int64_t nc, const Item *items, int nitems,
-                       const StepConst<R> &C, hipStream_t st);
+                       const StepConst<R> &C, const DiagBuf &out, int hist_len, hipStream_t st);
+// device address of the static diagnostics scratch of the current device:
+// set up once per device (pic_init), then read
+hipError_t diag_scratch_setup();
+void *diag_scratch();
 hipError_t launch_mj_table(double theta, double gamma_beta, double *cum, int M, int N, double *tab,
                            hipStream_t st);
 template <typename R> hipError_t launch_load_pairs(const BoxDev<R> *boxes, const LoadArgs &L, hipStream_t st);

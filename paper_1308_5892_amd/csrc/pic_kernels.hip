@@ -1702,7 +1702,8 @@ constexpr int kDiagNodes = 9 * 9 * 9;   // nodes of the largest tile (8^3 cells)
 constexpr int kDiagHist = 512;          // histograms up to this many bins are summed in LDS
 template <typename R>
 __global__ void __launch_bounds__(kBlock) diag_particles_kernel(const BoxDev<R> *__restrict__ boxes,
-                                                                const Item *__restrict__ items, StepConst<R> C)
+                                                                const Item *__restrict__ items, StepConst<R> C,
+                                                                DiagBuf out)
 {
     __shared__ R sE[3 * kDiagNodes];
     __shared__ double srho[kDiagNodes];
@@ -1771,7 +1772,7 @@ __global__ void __launch_bounds__(kBlock) diag_particles_kernel(const BoxDev<R> 
                 int bin = (int)floor((v - C.hist_lo) / (C.hist_hi - C.hist_lo) * C.hist_bins);
                 bin = bin < 0 ? 0 : (bin >= C.hist_bins ? C.hist_bins - 1 : bin);
                 if (lhist) atomicAdd(&shist[bin], 1u);
-                else atomicAdd(reinterpret_cast<unsigned long long *>(&B.hist[s * C.hist_bins + bin]), 1ull);
+                else atomicAdd(reinterpret_cast<unsigned long long *>(&out.hist[s * C.hist_bins + bin]), 1ull);
             }
             for (int kk = 0; kk < 2; ++kk)
                 for (int jj = 0; jj < 2; ++jj)
@@ -1784,15 +1785,15 @@ __global__ void __launch_bounds__(kBlock) diag_particles_kernel(const BoxDev<R> 
                         } else {
                             const int i = wrap_idx(ix + ii, B.n[0]), j = wrap_idx(iy + jj, B.n[1]),
                                       k = wrap_idx(iz + kk, B.n[2]);
-                            atomicAdd(&B.rho[i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)], q * w);
+                            atomicAdd(&out.rho[i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)], q * w);
                         }
                     }
         }
-        for (int k = 0; k < 6; ++k) block_sum_to<R>(&B.acc[kAccSp + 6 * s + k], acc[k]);
+        for (int k = 0; k < 6; ++k) block_sum_to<R>(&out.acc[kAccSp + 6 * s + k], acc[k]);
         if (lhist) {
             __syncthreads();
             for (int b = tid; b < C.hist_bins; b += kBlock)
-                if (shist[b]) atomicAdd(reinterpret_cast<unsigned long long *>(&B.hist[s * C.hist_bins + b]),
+                if (shist[b]) atomicAdd(reinterpret_cast<unsigned long long *>(&out.hist[s * C.hist_bins + b]),
                                         (unsigned long long)shist[b]);
             __syncthreads();
         }
@@ -1803,7 +1804,7 @@ __global__ void __launch_bounds__(kBlock) diag_particles_kernel(const BoxDev<R> 
             if (srho[q] != 0.0) {
                 const int i = wrap_idx(g.o[0] + q % g.NX, B.n[0]), j = wrap_idx(g.o[1] + (q / g.NX) % g.NY, B.n[1]),
                           k = wrap_idx(g.o[2] + q / (g.NX * g.NY), B.n[2]);
-                atomicAdd(&B.rho[i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)], srho[q]);
+                atomicAdd(&out.rho[i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)], srho[q]);
             }
     }
 }
@@ -1816,7 +1817,7 @@ __device__ inline void atomic_max_pos(double *p, double v)
 // Field energies (e^t, b^t) and the Gauss-law residual div e - rho at the nodes.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) diag_fields_kernel(const BoxDev<R> *__restrict__ boxes, int box,
-                                                             R dt, int filter)
+                                                             R dt, int filter, DiagBuf out)
 {
     const BoxDev<R> &B = boxes[box];
     const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1835,16 +1836,16 @@ __global__ void __launch_bounds__(kBlock) diag_fields_kernel(const BoxDev<R> *__
                            (double)fld(B.e, B, 1, i, j, k) - (double)fld(B.e, B, 1, i, j - 1, k) +
                            (double)fld(B.e, B, 2, i, j, k) - (double)fld(B.e, B, 2, i, j, k - 1);
         // with a smoothed current the conserved charge is the smoothed one
-        const double rho = filter ? smooth27<double>(B.rho, B.n, i, j, k) / 64.0 : B.rho[p];
+        const double rho = filter ? smooth27<double>(out.rho, B.n, i, j, k) / 64.0 : out.rho[p];
         const bool on_wall = B.wall >= 0 && (B.wall == 0 ? i : (B.wall == 1 ? j : k)) == 0;
         const double r = on_wall ? 0.0 : div - rho;   // a wall plane carries the conductor's surface charge
         v[6] = r * r;
         gmax = fabs(r);
     }
-    for (int q = 0; q < 6; ++q) block_sum_to<R>(&B.acc[kAccField + q], v[q]);
-    block_sum_to<R>(&B.acc[kAccField + 7], v[6]);
+    for (int q = 0; q < 6; ++q) block_sum_to<R>(&out.acc[kAccField + q], v[q]);
+    block_sum_to<R>(&out.acc[kAccField + 7], v[6]);
     for (int off = 32; off > 0; off >>= 1) gmax = fmax(gmax, __shfl_down(gmax, off));
-    if (__lane_id() == 0) atomic_max_pos(&B.acc[kAccField + 6], gmax);
+    if (__lane_id() == 0) atomic_max_pos(&out.acc[kAccField + 6], gmax);
 }
 
 // ----------------------------------------------------------- host launchers
@@ -1911,14 +1912,61 @@ hipError_t launch_repack(const BoxDev<R> *boxes, int nboxes, const Item *items, 
     return hipGetLastError();
 }
 
+// zero n 8-byte words (a kernel rather than a memset, so that a caller may
+// capture the diagnostics into a graph)
+// (a plain pointer parameter: an address-space qualifier on a kernel
+// parameter would give the device symbol another name than the host's)
+__global__ void __launch_bounds__(kBlock) zero_words_kernel(uint64_t *__restrict__ p, int64_t n)
+{
+    PIC_GLOBAL uint64_t *q = (PIC_GLOBAL uint64_t *)p;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n; t += (int64_t)gridDim.x * kBlock) q[t] = 0;
+}
+
 template <typename R>
 hipError_t launch_diag(const BoxDev<R> *boxes, int box, int64_t nc, const Item *items, int nitems,
-                       const StepConst<R> &C, hipStream_t st)
+                       const StepConst<R> &C, const DiagBuf &out, int hist_len, hipStream_t st)
 {
-    if (nitems) hipLaunchKernelGGL(diag_particles_kernel<R>, dim3(nitems), dim3(kBlock), 0, st, boxes, items, C);
+    // the accumulators, the charge density and the histogram start from zero
+    const int zb = 1024;
+    hipLaunchKernelGGL(zero_words_kernel, dim3(zb), dim3(kBlock), 0, st, (uint64_t *)out.acc, (int64_t)kAccLen);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(zb), dim3(kBlock), 0, st, (uint64_t *)out.rho, nc);
+    hipLaunchKernelGGL(zero_words_kernel, dim3(zb), dim3(kBlock), 0, st, (uint64_t *)out.hist, (int64_t)hist_len);
+    if (nitems)
+        hipLaunchKernelGGL(diag_particles_kernel<R>, dim3(nitems), dim3(kBlock), 0, st, boxes, items, C, out);
     const int nb = (int)((nc + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(diag_fields_kernel<R>, dim3(nb), dim3(kBlock), 0, st, boxes, box, C.dt, C.filter);
+    hipLaunchKernelGGL(diag_fields_kernel<R>, dim3(nb), dim3(kBlock), 0, st, boxes, box, C.dt, C.filter, out);
     return hipGetLastError();
+}
+
+// The diagnostics' own scratch for callers that cannot allocate device
+// memory: one array per GPU, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol); it uses the device address that hipGetSymbolAddress returns,
+// taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kDiagScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static void *scratch_ptr[kMaxDevices];
+
+hipError_t diag_scratch_setup()
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    if (scratch_ptr[dev]) return hipSuccess;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[dev] = p;
+    return hipSuccess;
+}
+
+void *diag_scratch()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    return scratch_ptr[dev];
 }
 
 // ------------------------------------------------- field Fourier spectra
@@ -2044,7 +2092,7 @@ hipError_t launch_spectrum(const BoxDev<R> *boxes, int box, const int n[3], int 
     template hipError_t launch_repack<R>(const BoxDev<R> *, int, const Item *, int, const StageItem *, int,    \
                                          const StepConst<R> &, hipStream_t);                                  \
     template hipError_t launch_diag<R>(const BoxDev<R> *, int, int64_t, const Item *, int,                    \
-                                       const StepConst<R> &, hipStream_t);                                    \
+                                       const StepConst<R> &, const DiagBuf &, int, hipStream_t);              \
     template hipError_t launch_spectrum<R>(const BoxDev<R> *, int, const int[3], int, int, int, R, double *,   \
                                            double *, hipStream_t);
 

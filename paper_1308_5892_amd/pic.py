@@ -26,7 +26,7 @@ ERROR_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ECOURANT", -3: "PIC_ENOME
 EXPORTED = ["pic_plan", "pic_init", "pic_load_maxwell_juttner", "pic_set_harris_field", "pic_step",
             "pic_diag", "pic_get_particles", "pic_set_particles", "pic_get_fields", "pic_set_fields",
             "pic_sync", "pic_steps_done", "pic_free", "pic_last_error", "pic_set_timing",
-            "pic_get_timing", "pic_autotune", "pic_field_spectrum"]
+            "pic_get_timing", "pic_autotune", "pic_field_spectrum", "pic_diag_noalloc"]
 
 
 class pic_species(C.Structure):
@@ -102,6 +102,7 @@ def lib():
         L.pic_set_harris_field.argtypes = [C.c_void_p, C.POINTER(pic_harris_field)]
         L.pic_step.argtypes = [C.c_void_p, C.c_int]
         L.pic_diag.argtypes = [C.c_void_p, C.c_int, C.POINTER(pic_diag_out), C.c_void_p]
+        L.pic_diag_noalloc.argtypes = [C.c_void_p, C.c_int, C.POINTER(pic_diag_out), C.c_void_p]
         L.pic_get_particles.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.POINTER(C.c_int64)]
         L.pic_set_particles.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -198,6 +199,14 @@ def pic_step(ctx, n):
 def pic_diag(ctx, box, hist=None):
     out = pic_diag_out()
     rc = lib().pic_diag(ctx, int(box), C.byref(out), _ptr(hist))
+    _check(rc, ctx)
+    return out
+
+
+def pic_diag_noalloc(ctx, box, hist=None):
+    """pic_diag summed in the library's static device scratch (no allocation)."""
+    out = pic_diag_out()
+    rc = lib().pic_diag_noalloc(ctx, int(box), C.byref(out), _ptr(hist))
     _check(rc, ctx)
     return out
 

@@ -38,6 +38,52 @@ def test_every_declared_symbol_is_exported(P):
     assert sorted(P.EXPORTED) == names
 
 
+def _device_kernel_names(lib_path, tmp_path):
+    """Kernel symbols of every gfx950 code object in the library's fat binary
+    (each translation unit contributes one offload bundle)."""
+    import struct
+    llvm = "/opt/rocm/llvm/bin"
+    blob = tmp_path / "fatbin.bin"
+    subprocess.check_call([f"{llvm}/llvm-objcopy", f"--dump-section=.hip_fatbin={blob}", lib_path,
+                           str(tmp_path / "copy.so")])
+    data = blob.read_bytes()
+    magic = b"__CLANG_OFFLOAD_BUNDLE__"
+    names, start, k = set(), data.find(magic), 0
+    while start >= 0:
+        n = struct.unpack_from("<Q", data, start + len(magic))[0]
+        pos = start + len(magic) + 8
+        for _ in range(n):
+            off, size, tl = struct.unpack_from("<QQQ", data, pos)
+            triple = data[pos + 24:pos + 24 + tl].decode()
+            pos += 24 + tl
+            if "gfx950" in triple:
+                co = tmp_path / f"co{k}.o"
+                k += 1
+                co.write_bytes(data[start + off:start + off + size])
+                out = subprocess.run([f"{llvm}/llvm-readelf", "--symbols", "-W", str(co)], capture_output=True,
+                                     text=True).stdout
+                names |= {m[:-3] for m in re.findall(r"\s(\S+\.kd)$", out, re.M)}
+        start = data.find(magic, start + 1)
+    return names, k
+
+
+def test_every_host_kernel_has_its_device_code(P, tmp_path):
+    # the host registers each kernel under its host-side mangled name; a
+    # kernel whose device name differs (an address-space qualifier on a
+    # parameter changes the mangling) is not found at launch
+    dev, nco = _device_kernel_names(P.LIB_PATH, tmp_path)
+    assert nco >= 2 and len(dev) > 20
+    out = subprocess.run(["nm", "--defined-only", P.LIB_PATH], capture_output=True, text=True).stdout
+    host = set()
+    for stub in re.findall(r"\s(_Z\S*__device_stub__\S+)$", out, re.M):
+        m = re.search(r"(\d+)__device_stub__", stub)
+        L = int(m.group(1))
+        host.add(stub[:m.start()] + str(L - len("__device_stub__")) + stub[m.end():])
+    assert len(host) > 20
+    missing = sorted(host - dev)
+    assert not missing, missing
+
+
 def test_struct_layout_matches_header(P, tmp_path):
     structs = {
         "pic_species": P.pic_species, "pic_box": P.pic_box, "pic_config": P.pic_config,

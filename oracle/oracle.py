@@ -55,13 +55,15 @@ def lib():
         L.orc_deposit_move.restype = C.c_int
         L.orc_deposit_charge.argtypes = [G, C.c_double, _dp, _dp]
         L.orc_step.argtypes = [G, C.c_double, C.c_double, C.c_int, _dp, _dp, C.c_int64,
-                               _ip, _dp, _dp, _dp, _dp, C.c_int, C.c_int, C.c_int]
+                               _ip, _dp, _dp, _dp, _dp, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.orc_curl_e4.argtypes = [G, _dp, _dp]
+        L.orc_advance_b4.argtypes = [G, C.c_double, _dp, _dp]
         L.orc_filter27.argtypes = [G, C.c_int, _dp]
         L.orc_wall_fields.argtypes = [G, C.c_int, _dp, _dp]
         L.orc_backward_half.argtypes = [G, C.c_double, _dp, C.c_int64, _ip, _dp, _dp, _dp, _dp]
         L.orc_diag.argtypes = [G, C.c_double, C.c_double, C.c_int, _dp, _dp, _dp, C.c_int64,
                                _ip, _dp, _dp, _dp, _dp, _dp, C.c_int, C.c_double, C.c_double,
-                               C.c_void_p, C.c_int, C.c_int]
+                               C.c_void_p, C.c_int, C.c_int, C.c_int]
         L.orc_philox4x64.argtypes = [_up, _up, _up]
         L.orc_mj_range.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_mj_table.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, _dp]
@@ -93,6 +95,21 @@ def curl_e(dims, e):
     out = np.zeros_like(_f(e))
     lib().orc_curl_e(_g(dims), _f(e), out)
     return out
+
+
+def curl_e4(dims, e):
+    """Fourth-order curl of e at the b positions (the fourth-order solver of
+    App. A.3.2; reading in pic_oracle.c)."""
+    out = np.zeros_like(_f(e))
+    lib().orc_curl_e4(_g(dims), _f(e), out)
+    return out
+
+
+def advance_b4(dims, h, e, b):
+    """Return b - h curl4 e (Faraday's law of the fourth-order solver)."""
+    b = _f(b).copy()
+    lib().orc_advance_b4(_g(dims), float(h), _f(e), b)
+    return b
 
 
 def curl_b(dims, b):
@@ -196,6 +213,7 @@ class State:
         self.species = np.zeros(0, dtype=np.int32)
         self.filter = False                      # smooth the current (App. A.3.4)
         self.wall = -1                           # axis with conducting walls (App. A.4), -1: none
+        self.faraday4 = False                    # fourth-order curl in Faraday's law (App. A.3.2)
 
     def add_particles(self, s, x, u):
         self.x = np.concatenate([self.x, _f(x).reshape(-1, 3)])
@@ -208,7 +226,7 @@ class State:
         u = np.ascontiguousarray(self.u).reshape(-1)
         lib().orc_step(_g(self.dims), self.dt, self.alpha0, len(self.kq), self.kq, self.sgn,
                        len(self.species), np.ascontiguousarray(self.species), x, u,
-                       self.e, self.b, int(nsteps), int(self.filter), int(self.wall))
+                       self.e, self.b, int(nsteps), int(self.filter), int(self.wall), int(self.faraday4))
         self.x = x.reshape(-1, 3)
         self.u = u.reshape(-1, 3)
 
@@ -219,11 +237,14 @@ class State:
         lib().orc_backward_half(_g(self.dims), self.dt, self.kq, len(self.species),
                                 np.ascontiguousarray(self.species), x, u, self.e, self.b)
         self.u = u.reshape(-1, 3)
-        self.b = advance_b(self.dims, -0.5 * self.dt, self.e, self.b)
+        self.b = self._advance_b(-0.5 * self.dt, self.e, self.b)
+
+    def _advance_b(self, h, e, b):
+        return (advance_b4 if self.faraday4 else advance_b)(self.dims, h, e, b)
 
     def b_at_t(self):
         """b^t = b^{t-dt/2} - (dt/2) curl e^t (App. A.3.1 item 1)."""
-        return advance_b(self.dims, 0.5 * self.dt, self.e, self.b)
+        return self._advance_b(0.5 * self.dt, self.e, self.b)
 
     def diag(self, nbins=0, lo=-4.0, hi=3.0):
         nsp = len(self.kq)
@@ -234,7 +255,8 @@ class State:
         lib().orc_diag(_g(self.dims), self.dt, self.alpha0, nsp, self.kq, self.sgn, self.m,
                        len(self.species), np.ascontiguousarray(self.species), x, u,
                        self.e, self.b, out, int(nbins), float(lo), float(hi),
-                       hist.ctypes.data if nbins > 0 else None, int(self.filter), int(self.wall))
+                       hist.ctypes.data if nbins > 0 else None, int(self.filter), int(self.wall),
+                       int(self.faraday4))
         d = {
             "W_E": out[0:3].copy(), "W_B": out[3:6].copy(),
             "gauss_max": out[6], "gauss_rms": out[7],

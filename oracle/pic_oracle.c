@@ -120,6 +120,62 @@ void orc_advance_b(const int g[3], double h, const double *e, double *b)
     free(c);
 }
 
+/*
+ * Fourth-order curl of e at the b positions, for the fourth-order field
+ * solver the paper adds against numerical Cerenkov emission (App. A.3.2,
+ * last paragraph; App. B, third item).  READING (the paper names the solver
+ * but prints no stencil): every difference along an axis is the staggered
+ * fourth-order one,
+ *   d_a f (x) = (9/8) (f(x + 1/2) - f(x - 1/2)) - (1/24) (f(x + 3/2) - f(x - 3/2)),
+ * and only Faraday's law uses it; Ampere's law keeps the second-order curl,
+ * so the discrete divergence of e (second order) still changes only by the
+ * charge-conserving current and Gauss's law holds as with Yee.
+ */
+static double d4(const double *F, const int g[3], int c, int i, int j, int k, int a)
+{
+    /* d_a of component c at the point half a cell above (i,j,k) along a */
+    int o[3] = {0, 0, 0};
+    o[a] = 1;
+    double near = at(F, g, c, i + o[0], j + o[1], k + o[2]) - at(F, g, c, i, j, k);
+    double far = at(F, g, c, i + 2 * o[0], j + 2 * o[1], k + 2 * o[2])
+               - at(F, g, c, i - o[0], j - o[1], k - o[2]);
+    return 9.0 / 8.0 * near - 1.0 / 24.0 * far;
+}
+
+void orc_curl_e4(const int g[3], const double *e, double *out)
+{
+    int64_t n = ncells(g);
+    for (int k = 0; k < g[2]; ++k)
+        for (int j = 0; j < g[1]; ++j)
+            for (int i = 0; i < g[0]; ++i) {
+                int64_t p = cell_index(g, i, j, k);
+                /* (curl e)_x at (i, j+1/2, k+1/2) = d_y e_z - d_z e_y */
+                out[0 * n + p] = d4(e, g, 2, i, j, k, 1) - d4(e, g, 1, i, j, k, 2);
+                /* (curl e)_y at (i+1/2, j, k+1/2) = d_z e_x - d_x e_z */
+                out[1 * n + p] = d4(e, g, 0, i, j, k, 2) - d4(e, g, 2, i, j, k, 0);
+                /* (curl e)_z at (i+1/2, j+1/2, k) = d_x e_y - d_y e_x */
+                out[2 * n + p] = d4(e, g, 1, i, j, k, 0) - d4(e, g, 0, i, j, k, 1);
+            }
+}
+
+/* b <- b - h * curl e with the fourth-order curl (orc_curl_e4) */
+void orc_advance_b4(const int g[3], double h, const double *e, double *b)
+{
+    int64_t n3 = 3 * ncells(g);
+    double *c = (double *)malloc(sizeof(double) * n3);
+    orc_curl_e4(g, e, c);
+    for (int64_t p = 0; p < n3; ++p)
+        b[p] -= h * c[p];
+    free(c);
+}
+
+/* Faraday half or full advance with the solver's curl of e */
+static void advance_b_order(const int g[3], double h, const double *e, double *b, int faraday4)
+{
+    if (faraday4) orc_advance_b4(g, h, e, b);
+    else orc_advance_b(g, h, e, b);
+}
+
 /* e <- e + h * curl b  (full advance with h = dt; App. A.3.1 step 6) */
 void orc_advance_e(const int g[3], double h, const double *b, double *e)
 {
@@ -413,11 +469,12 @@ void orc_filter27(const int g[3], int ncomp, double *f)
  * wall in {0, 1, 2} puts perfectly conducting walls at the two box faces
  * normal to that axis (App. A.4; see orc_wall_fields and the move below);
  * wall = -1: every boundary is periodic.
+ * faraday4 != 0 advances b with the fourth-order curl of e (orc_curl_e4).
  */
 void orc_step(const int g[3], double dt, double alpha0, int nsp,
               const double *kq, const double *sgn, int64_t np,
               const int32_t *species, double *x, double *u,
-              double *e, double *b, int nsteps, int filter, int wall)
+              double *e, double *b, int nsteps, int filter, int wall, int faraday4)
 {
     int64_t n = ncells(g);
     double *J = (double *)malloc(sizeof(double) * 3 * n);
@@ -427,7 +484,7 @@ void orc_step(const int g[3], double dt, double alpha0, int nsp,
     char *hit = (char *)calloc((size_t)(np > 0 ? np : 1), 1);
     for (int it = 0; it < nsteps; ++it) {
         /* 1. b^{t-dt/2} -> b^t */
-        orc_advance_b(g, 0.5 * dt, e, b);
+        advance_b_order(g, 0.5 * dt, e, b, faraday4);
         if (wall >= 0) orc_wall_fields(g, wall, e, b);
         /* 2-3. velocity with e^t, b^t at x^t; then position to t+dt */
         for (int64_t p = 0; p < np; ++p) {
@@ -466,7 +523,7 @@ void orc_step(const int g[3], double dt, double alpha0, int nsp,
             }
         }
         /* 4. b^t -> b^{t+dt/2} */
-        orc_advance_b(g, 0.5 * dt, e, b);
+        advance_b_order(g, 0.5 * dt, e, b, faraday4);
         if (wall >= 0) orc_wall_fields(g, wall, e, b);
         /* 6. e^t -> e^{t+dt} with curl b^{t+dt/2} */
         orc_advance_e(g, dt, b, e);
@@ -531,19 +588,20 @@ void orc_backward_half(const int g[3], double dt, const double *kq, int64_t np,
  * gamma^t = sqrt(1 + |u^-|^2), u^- = u^{t-dt/2} + (k dt/2) E(x^t) - the same
  * gamma^t the mover uses.
  * hist (optional, nsp x nbins): counts of log10(gamma^t - 1) in [lo, hi),
- * clamped to the end bins.
+ * clamped to the end bins.  faraday4: b^t is formed with the fourth-order
+ * curl of e, as the cycle forms it.
  */
 void orc_diag(const int g[3], double dt, double alpha0, int nsp, const double *kq,
               const double *sgn, const double *m_over_me, int64_t np,
               const int32_t *species, const double *x, const double *u,
               const double *e, const double *b, double *out,
-              int nbins, double lo, double hi, int64_t *hist, int filter, int wall)
+              int nbins, double lo, double hi, int64_t *hist, int filter, int wall, int faraday4)
 {
     int64_t n = ncells(g);
     double *bt = (double *)malloc(sizeof(double) * 3 * n);
     double *rho = (double *)calloc((size_t)n, sizeof(double));
     memcpy(bt, b, sizeof(double) * 3 * n);
-    orc_advance_b(g, 0.5 * dt, e, bt);
+    advance_b_order(g, 0.5 * dt, e, bt, faraday4);
     for (int c = 0; c < 3; ++c) {
         double we = 0.0, wb = 0.0;
         for (int64_t p = 0; p < n; ++p) {

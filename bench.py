@@ -172,10 +172,13 @@ WORKLOAD_TEXT = {
 }
 
 
-def time_form(wl, fp64, steps, warmup, sort_interval):
+def time_form(wl, fp64, steps, warmup, sort_interval, made=None):
+    """Load a workload (or take the loaded `made` = make_sim(...)), run
+    `warmup` untimed steps, then time `steps` steps; the push and field
+    kernels are timed by the library's events."""
     import torch
     from paper_1308_5892_amd import pic as P
-    sim, npart, cells = make_sim(wl, fp64, sort_interval)
+    sim, npart, cells = made if made is not None else make_sim(wl, fp64, sort_interval)
     torch.cuda.synchronize()
     if warmup:
         sim.step(warmup)
@@ -197,24 +200,49 @@ def time_form(wl, fp64, steps, warmup, sort_interval):
     return {"seconds": t1 - t0, "npart": npart, "cells": cells, "timing": tm, "diag": d}
 
 
-def cpu_baseline(w):
-    """The FP64 oracle, single-threaded, on 32^3 cells at the workload's density
-    and temperature: pushes per second over 4 full steps (about 13 s)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, all_steps=3):
+    """The FP64 oracle on this host's cores, on the workload's own shape (its
+    cells, density and temperature), built -O3 -march=native with OpenMP:
+    loaded and integrated back by dt/2 with all threads, then one full step on
+    one thread and `all_steps` full steps on all threads (OMP_NUM_THREADS, else
+    every core), each timed."""
     from oracle import oracle as O
-    dims = (32, 32, 32)
-    npairs = w["ppc"] * 32 ** 3
+    L = O.lib_native()
+    nthreads = L.orc_threads(0)
+    dims = tuple(w["dims"])
+    npairs = w["ppc"] * dims[0] * dims[1] * dims[2]
     sp = {"theta": w["theta"], "gb": 0.0, "axis": 1}
-    x, ua, ub = O.load_pairs(dims, w["seed"], 0, npairs, sp, sp)
-    st = O.State(dims, w["dt"], w["n_x"], 2.0 * w["ppc"], [(-1.0, 1.0), (1.0, 1.0)])
+    x, ua, ub = O.load_pairs(dims, w["seed"], 0, npairs, sp, sp, lib_=L)
+    st = O.State(dims, w["dt"], w["n_x"], 2.0 * w["ppc"], [(-1.0, 1.0), (1.0, 1.0)], L=L)
     st.add_particles(0, x, ua)
     st.add_particles(1, x, ub)
-    nsteps = 4
+    del x, ua, ub
+    st.backward_half()
+    L.orc_threads(1)
     t0 = time.perf_counter()
-    st.step(nsteps)
-    dt = time.perf_counter() - t0
-    return {"value": 2 * npairs * nsteps / dt, "unit": "pushes/s", "cores": 1, "kind": "oracle",
-            "sample": f"32^3 cells at {w['ppc']} pairs/cell, theta={w['theta']}, {nsteps} full steps "
-                      f"({2 * npairs * nsteps} pushes, {dt:.1f} s), single thread"}
+    st.step(1)
+    t1 = time.perf_counter() - t0
+    L.orc_threads(nthreads)
+    t0 = time.perf_counter()
+    st.step(all_steps)
+    tn = time.perf_counter() - t0
+    one = 2 * npairs / t1
+    return {"value": 2 * npairs * all_steps / tn, "unit": "pushes/s", "cores": nthreads, "kind": "oracle",
+            "single_thread": one, "host": {"nproc": os.cpu_count(), "cpu_model": cpu_model()},
+            "build": "gcc -O3 -march=native -fopenmp (per-thread current, added in thread order)",
+            "sample": f"{dims[0]}x{dims[1]}x{dims[2]} cells at {w['ppc']} pairs/cell, theta={w['theta']} "
+                      f"(the workload itself): {all_steps} full steps on {nthreads} threads "
+                      f"({2 * npairs * all_steps} pushes, {tn:.1f} s) and 1 step on one thread ({t1:.1f} s)"}
 
 
 def copy_calibration(nbytes):
@@ -247,6 +275,8 @@ def main():
                     help="smooth the current with the 27-point filter before it enters e")
     ap.add_argument("--autotune", action="store_true",
                     help="pick tile shapes and sort interval with pic_autotune before timing")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="thermal64: skip timing the beam, Harris and ensemble workloads")
     ap.add_argument("--no-breakdown", action="store_true",
                     help="ensemble: skip timing each box class (by pairs per cell) in its own launch")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -276,8 +306,18 @@ def main():
         shapes = sorted({tuple(b["tile"]) for b in boxes})
         tune.update({"tiles": [list(t) for t in shapes], "sort_interval": sort_interval})
         log(f"autotune: {tune}")
+    # The FP32 workload is loaded first, then the FP64 form is measured, then
+    # the FP32 warm-up and timed steps follow at once: a GPU that starts
+    # pushing from idle runs the push 10-20 % slower over its first ~30 steps
+    # (its clock settling; the same after any pause of a second), and the
+    # FP64 steps take it past that.
+    made32 = make_sim(spec, False, sort_interval)
+    fp64 = None
+    if not args.no_fp64:
+        log(f"FP64 form: {args.fp64_steps} timed steps")
+        r64 = time_form(spec, True, args.fp64_steps, 5, sort_interval)
     log(f"FP32 form: {WORKLOAD_TEXT[wl]}, {args.warmup} warmup + {args.steps} timed steps")
-    r32 = time_form(spec, False, args.steps, args.warmup, sort_interval)
+    r32 = time_form(spec, False, args.steps, args.warmup, sort_interval, made=made32)
     npart, cells = r32["npart"], r32["cells"]
     value = npart * args.steps / r32["seconds"]
     tm = r32["timing"]
@@ -292,16 +332,19 @@ def main():
         f"({achieved:.0f} GB/s), fields {tm['field_ms'] / max(1, tm['field_launches']):.3f} ms/step, "
         f"sort {tm['sort_ms']:.1f} ms total")
 
-    fp64 = None
     if not args.no_fp64:
-        log(f"FP64 form: {args.fp64_steps} timed steps")
-        r64 = time_form(spec, True, args.fp64_steps, 5, sort_interval)
         v64 = r64["npart"] * args.fp64_steps / r64["seconds"]
         t64 = r64["timing"]
         p64 = t64["push_ms"] / max(1, t64["push_launches"]) / 1e3
-        b64 = 104.0 * npart + 96.0 * cells   # 52 B state each way, 6 x 8 B fields, 3 x 8 B current
+        # this build's FP64 state is 52 B (int32 cell, 3 FP64 offsets, 3 FP64
+        # u), read and written; the plain FP64 form's count is 48 B (six FP64
+        # values) each way; both with 6 x 8 B fields read and 3 x 8 B current
+        # flushed per cell
+        b64 = 104.0 * npart + 72.0 * cells
+        b64_plain = 96.0 * npart + 72.0 * cells
         fp64 = {"value": v64, "unit": "pushes/s", "steps": args.fp64_steps,
                 "push_kernel_ms": p64 * 1e3, "roofline_frac": b64 / p64 / 1e9 / HBM_PEAK_GBS,
+                "roofline_frac_96B": b64_plain / p64 / 1e9 / HBM_PEAK_GBS,
                 "speedup_fp32_over_fp64": value / v64}
         log(f"FP64: {v64 / 1e9:.2f} G pushes/s, speedup {value / v64:.2f}x")
 
@@ -310,6 +353,26 @@ def main():
         log("CPU oracle baseline (bounded sample)")
         cpu = cpu_baseline(W.THERMAL64)
         log(f"CPU: {cpu['value'] / 1e6:.2f} M pushes/s")
+
+    workloads = None
+    if wl == "thermal64" and not args.no_workloads:
+        # the other workload families under the same clock: same tiles, sort
+        # interval, warm-up and timed steps as the headline
+        workloads = []
+        for name in ("beams", "harris", "ensemble"):
+            sub = workload(name, tuple(args.tile))
+            log(f"workload {name}: {WORKLOAD_TEXT[name]}")
+            rw = time_form(sub, False, args.steps, args.warmup, sort_interval)
+            tw = rw["timing"]
+            pw = tw["push_ms"] / max(1, tw["push_launches"]) / 1e3
+            bw = 56.0 * rw["npart"] + 48.0 * rw["cells"]
+            workloads.append({"workload": WORKLOAD_TEXT[name], "particles": rw["npart"], "cells": rw["cells"],
+                              "pushes_per_s": rw["npart"] * args.steps / rw["seconds"],
+                              "ms_per_step": rw["seconds"] / args.steps * 1e3,
+                              "push_kernel_ms": pw * 1e3, "roofline_frac": bw / pw / 1e9 / HBM_PEAK_GBS,
+                              "flags": rw["diag"]["flags"], "overflow": rw["diag"]["n_overflow"]})
+            log(f"  {workloads[-1]['pushes_per_s'] / 1e9:.2f} G pushes/s, push {pw * 1e3:.3f} ms, "
+                f"roofline {workloads[-1]['roofline_frac']:.3f}")
 
     classes = None
     if wl == "ensemble" and not args.no_breakdown:
@@ -349,6 +412,7 @@ def main():
         "cpu_baseline": cpu,
         "fp64_form": fp64,
         "classes": classes,
+        "workloads": workloads,
         "check": {"flags": d["flags"], "particles": d["count"], "gauss_max": d["gauss_max"],
                   "overflow": d["n_overflow"]},
     }

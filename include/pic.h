@@ -69,6 +69,14 @@ extern "C" {
                                   1/4 for the 12 edge and 1/8 for the 8 corner neighbours,
                                   normalised to one); the Gauss residual of pic_diag then uses
                                   the charge smoothed the same way */
+#define PIC_FARADAY4 8u        /* fourth-order field solver against numerical Cerenkov emission
+                                  (App. A.3.2, last paragraph; App. B, third item): Faraday's law
+                                  takes the staggered fourth-order difference along each axis,
+                                  (9/8)(f[+1/2] - f[-1/2]) - (1/24)(f[+3/2] - f[-3/2]); Ampere's law
+                                  keeps the second-order curl, so Gauss's law holds as with Yee.
+                                  Vacuum dispersion: (2/dt)^2 sin^2(w dt/2) = sum_a [4 sin^2(k_a/2)
+                                  + (2/3) sin^4(k_a/2)]; Courant bound dt < 2/sqrt(14) = 0.5345;
+                                  not with walls */
 
 /* pic_load_desc.profile */
 #define PIC_PROFILE_UNIFORM 0
@@ -103,7 +111,7 @@ typedef struct pic_config {
     pic_species        species[PIC_MAX_SPECIES];
     double             dt;          /* time step in X0/c */
     int32_t            sort_interval;  /* steps between counting-sort repacks; 0 = never */
-    uint32_t           flags;       /* PIC_FP64_FORM | PIC_TRACK_IDS */
+    uint32_t           flags;       /* PIC_FP64_FORM | PIC_TRACK_IDS | PIC_FILTER_CURRENT | PIC_FARADAY4 */
     int32_t            hist_bins;   /* bins of the log10(gamma-1) histogram in pic_diag (0 = none) */
     double             hist_lo, hist_hi;   /* histogram range of log10(gamma - 1) */
     double             headroom;    /* particle slots per particle (>= 1.05; 0 = 1.3) */

@@ -26,8 +26,12 @@ _lp = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 _up = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
 
 
+_LIB_NATIVE = os.path.join(_HERE, "liboracle_native.so")
+
+
 def build(force: bool = True) -> str:
-    """Compile liboracle.so next to its source with gcc (plain C11, -O2)."""
+    """Compile liboracle.so next to its source with gcc (plain C11, -O2): the
+    serial oracle that the tests and the smoke check use."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
@@ -35,7 +39,30 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_native() -> str:
+    """The same source built for timing the oracle on this host's cores:
+    -O3 -march=native with OpenMP (parallel particle loops, one current array
+    per thread added in thread order)."""
+    tmp = _LIB_NATIVE + ".tmp"
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-fopenmp", "-std=c11", "-fPIC", "-shared", "-o", tmp,
+                           _SRC, "-lm"])
+    os.replace(tmp, _LIB_NATIVE)
+    return _LIB_NATIVE
+
+
 _lib = None
+_lib_native = None
+
+
+def lib_native():
+    """Handle of the native OpenMP build, compiled on its first use in the
+    process (-march=native is this host's: a copy built elsewhere is never
+    loaded)."""
+    global _lib_native
+    if _lib_native is None:
+        build_native()
+        _lib_native = _bind(C.CDLL(_LIB_NATIVE))
+    return _lib_native
 
 
 def lib():
@@ -43,41 +70,47 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        L = C.CDLL(_LIB)
-        G = np.ctypeslib.ndpointer(dtype=np.int32, shape=(3,), flags="C_CONTIGUOUS")
-        L.orc_curl_e.argtypes = [G, _dp, _dp]
-        L.orc_curl_b.argtypes = [G, _dp, _dp]
-        L.orc_advance_b.argtypes = [G, C.c_double, _dp, _dp]
-        L.orc_advance_e.argtypes = [G, C.c_double, _dp, _dp]
-        L.orc_gather.argtypes = [G, _dp, _dp, _dp, _dp, _dp]
-        L.orc_boris.argtypes = [C.c_double, C.c_double, _dp, _dp, _dp]
-        L.orc_deposit_move.argtypes = [G, C.c_double, _dp, _dp, _dp]
-        L.orc_deposit_move.restype = C.c_int
-        L.orc_deposit_charge.argtypes = [G, C.c_double, _dp, _dp]
-        L.orc_step.argtypes = [G, C.c_double, C.c_double, C.c_int, _dp, _dp, C.c_int64,
-                               _ip, _dp, _dp, _dp, _dp, C.c_int, C.c_int, C.c_int, C.c_int]
-        L.orc_curl_e4.argtypes = [G, _dp, _dp]
-        L.orc_advance_b4.argtypes = [G, C.c_double, _dp, _dp]
-        L.orc_filter27.argtypes = [G, C.c_int, _dp]
-        L.orc_wall_fields.argtypes = [G, C.c_int, _dp, _dp]
-        L.orc_backward_half.argtypes = [G, C.c_double, _dp, C.c_int64, _ip, _dp, _dp, _dp, _dp]
-        L.orc_diag.argtypes = [G, C.c_double, C.c_double, C.c_int, _dp, _dp, _dp, C.c_int64,
-                               _ip, _dp, _dp, _dp, _dp, _dp, C.c_int, C.c_double, C.c_double,
-                               C.c_void_p, C.c_int, C.c_int, C.c_int]
-        L.orc_philox4x64.argtypes = [_up, _up, _up]
-        L.orc_mj_range.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
-        L.orc_mj_table.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, _dp]
-        L.orc_mj_radial.argtypes = [C.c_double, C.c_double]
-        L.orc_mj_radial.restype = C.c_double
-        L.orc_mj_draw.argtypes = [_dp, C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
-                                  C.c_double, C.c_double, _dp]
-        L.orc_load_pairs.argtypes = [G, C.c_uint64, C.c_uint64, C.c_int64, C.c_int, C.c_int,
-                                     C.c_double, C.c_double, C.c_double, _dp, _dp, C.c_int,
-                                     C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
-                                     C.c_int, _dp, _dp, _dp]
-        L.orc_harris_params.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _dp]
-        _lib = L
+        _lib = _bind(C.CDLL(_LIB))
     return _lib
+
+
+def _bind(L):
+    """Argument types of every oracle entry point on a loaded build."""
+    G = np.ctypeslib.ndpointer(dtype=np.int32, shape=(3,), flags="C_CONTIGUOUS")
+    L.orc_curl_e.argtypes = [G, _dp, _dp]
+    L.orc_curl_b.argtypes = [G, _dp, _dp]
+    L.orc_advance_b.argtypes = [G, C.c_double, _dp, _dp]
+    L.orc_advance_e.argtypes = [G, C.c_double, _dp, _dp]
+    L.orc_gather.argtypes = [G, _dp, _dp, _dp, _dp, _dp]
+    L.orc_boris.argtypes = [C.c_double, C.c_double, _dp, _dp, _dp]
+    L.orc_deposit_move.argtypes = [G, C.c_double, _dp, _dp, _dp]
+    L.orc_deposit_move.restype = C.c_int
+    L.orc_deposit_charge.argtypes = [G, C.c_double, _dp, _dp]
+    L.orc_step.argtypes = [G, C.c_double, C.c_double, C.c_int, _dp, _dp, C.c_int64,
+                           _ip, _dp, _dp, _dp, _dp, C.c_int, C.c_int, C.c_int, C.c_int]
+    L.orc_curl_e4.argtypes = [G, _dp, _dp]
+    L.orc_advance_b4.argtypes = [G, C.c_double, _dp, _dp]
+    L.orc_filter27.argtypes = [G, C.c_int, _dp]
+    L.orc_wall_fields.argtypes = [G, C.c_int, _dp, _dp]
+    L.orc_backward_half.argtypes = [G, C.c_double, _dp, C.c_int64, _ip, _dp, _dp, _dp, _dp]
+    L.orc_diag.argtypes = [G, C.c_double, C.c_double, C.c_int, _dp, _dp, _dp, C.c_int64,
+                           _ip, _dp, _dp, _dp, _dp, _dp, C.c_int, C.c_double, C.c_double,
+                           C.c_void_p, C.c_int, C.c_int, C.c_int]
+    L.orc_philox4x64.argtypes = [_up, _up, _up]
+    L.orc_mj_range.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.orc_mj_table.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, _dp]
+    L.orc_mj_radial.argtypes = [C.c_double, C.c_double]
+    L.orc_mj_radial.restype = C.c_double
+    L.orc_mj_draw.argtypes = [_dp, C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
+                              C.c_double, C.c_double, _dp]
+    L.orc_load_pairs.argtypes = [G, C.c_uint64, C.c_uint64, C.c_int64, C.c_int, C.c_int,
+                                 C.c_double, C.c_double, C.c_double, _dp, _dp, C.c_int,
+                                 C.c_double, C.c_double, C.c_int, C.c_double, C.c_double,
+                                 C.c_int, _dp, _dp, _dp]
+    L.orc_harris_params.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, _dp]
+    L.orc_threads.argtypes = [C.c_int]
+    L.orc_threads.restype = C.c_int
+    return L
 
 
 def _g(dims):
@@ -196,8 +229,10 @@ def deposit_charge(dims, sgn, x, rho=None):
 class State:
     """Plain FP64 PIC state: x^t, u^{t-dt/2}, e^t, b^{t-dt/2} (App. A.3.1)."""
 
-    def __init__(self, dims, dt, n_x, rho0, species):
-        """species: list of (q_over_e, m_over_me)."""
+    def __init__(self, dims, dt, n_x, rho0, species, L=None):
+        """species: list of (q_over_e, m_over_me).  L: the oracle build to run
+        (default: the serial parity build)."""
+        self.L = lib() if L is None else L
         self.dims = tuple(int(d) for d in dims)
         self.n = int(np.prod(self.dims))
         self.dt = float(dt)
@@ -224,7 +259,7 @@ class State:
     def step(self, nsteps=1):
         x = np.ascontiguousarray(self.x).reshape(-1)
         u = np.ascontiguousarray(self.u).reshape(-1)
-        lib().orc_step(_g(self.dims), self.dt, self.alpha0, len(self.kq), self.kq, self.sgn,
+        self.L.orc_step(_g(self.dims), self.dt, self.alpha0, len(self.kq), self.kq, self.sgn,
                        len(self.species), np.ascontiguousarray(self.species), x, u,
                        self.e, self.b, int(nsteps), int(self.filter), int(self.wall), int(self.faraday4))
         self.x = x.reshape(-1, 3)
@@ -234,7 +269,7 @@ class State:
         """u^0 -> u^{-dt/2} and b^0 -> b^{-dt/2} (App. A.3.1, before the loop)."""
         u = np.ascontiguousarray(self.u).reshape(-1).copy()
         x = np.ascontiguousarray(self.x).reshape(-1)
-        lib().orc_backward_half(_g(self.dims), self.dt, self.kq, len(self.species),
+        self.L.orc_backward_half(_g(self.dims), self.dt, self.kq, len(self.species),
                                 np.ascontiguousarray(self.species), x, u, self.e, self.b)
         self.u = u.reshape(-1, 3)
         self.b = self._advance_b(-0.5 * self.dt, self.e, self.b)
@@ -252,7 +287,7 @@ class State:
         hist = np.zeros(max(nsp * nbins, 1), dtype=np.int64)
         x = np.ascontiguousarray(self.x).reshape(-1)
         u = np.ascontiguousarray(self.u).reshape(-1)
-        lib().orc_diag(_g(self.dims), self.dt, self.alpha0, nsp, self.kq, self.sgn, self.m,
+        self.L.orc_diag(_g(self.dims), self.dt, self.alpha0, nsp, self.kq, self.sgn, self.m,
                        len(self.species), np.ascontiguousarray(self.species), x, u,
                        self.e, self.b, out, int(nbins), float(lo), float(hi),
                        hist.ctypes.data if nbins > 0 else None, int(self.filter), int(self.wall),
@@ -300,7 +335,7 @@ def mj_radial(a, w):
 
 
 def load_pairs(dims, seed, stream, npairs, A, B, profile=0, paxis=0, centre=0.0, L=1.0,
-               halfw=1.0, N=1 << 16, tabA=None, tabB=None):
+               halfw=1.0, N=1 << 16, tabA=None, tabB=None, lib_=None):
     """Co-located pairs (Sect. 2.1) with drifting Maxwell-Juttner momenta (App. D).
 
     A, B: dicts with theta, gb (signed Gamma*beta) and axis (drift axis).
@@ -311,7 +346,8 @@ def load_pairs(dims, seed, stream, npairs, A, B, profile=0, paxis=0, centre=0.0,
     x = np.zeros(3 * npairs)
     uA = np.zeros(3 * npairs)
     uB = np.zeros(3 * npairs)
-    lib().orc_load_pairs(_g(dims), int(seed), int(stream), int(npairs), int(profile), int(paxis),
+    (lib() if lib_ is None else lib_).orc_load_pairs(_g(dims), int(seed), int(stream), int(npairs), int(profile),
+                                                     int(paxis),
                          float(centre), float(L), float(halfw), _f(tabA), _f(tabB), int(N),
                          float(A["theta"]), float(A["gb"]), int(A["axis"]),
                          float(B["theta"]), float(B["gb"]), int(B["axis"]), x, uA, uB)

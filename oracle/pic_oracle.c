@@ -27,11 +27,20 @@
  * Parity status: every function below is pinned by a CPU test (closed forms,
  * brute force, printed values, a library Philox, Monte-Carlo moments); see the
  * tests directory.
+ *
+ * Threads: built with OpenMP (only for timing the oracle on all host cores),
+ * the independent per-particle loops of the loader, the backward half step
+ * and the cycle run in parallel, and the deposit sums into one current array
+ * per thread, added in thread order; built without it (the parity build),
+ * every loop runs in order.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
@@ -482,11 +491,18 @@ void orc_step(const int g[3], double dt, double alpha0, int nsp,
     (void)nsp;
     double *xwall = (double *)malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
     char *hit = (char *)calloc((size_t)(np > 0 ? np : 1), 1);
+#ifdef _OPENMP
+    const int nthr = omp_get_max_threads();
+    double *Jt = (double *)malloc(sizeof(double) * 3 * n * (size_t)nthr);
+#endif
     for (int it = 0; it < nsteps; ++it) {
         /* 1. b^{t-dt/2} -> b^t */
         advance_b_order(g, 0.5 * dt, e, b, faraday4);
         if (wall >= 0) orc_wall_fields(g, wall, e, b);
         /* 2-3. velocity with e^t, b^t at x^t; then position to t+dt */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
         for (int64_t p = 0; p < np; ++p) {
             double E[3], B[3];
             int s = species[p];
@@ -530,6 +546,29 @@ void orc_step(const int g[3], double dt, double alpha0, int nsp,
         /* 9. currents from the moves x^t -> x^{t+dt} (READING: the appendix's
          *    old position plus displacement, not item 9's wording) */
         memset(J, 0, sizeof(double) * 3 * n);
+#ifdef _OPENMP
+#pragma omp parallel
+        {
+            double *Jm = Jt + (size_t)omp_get_thread_num() * 3 * n;
+            memset(Jm, 0, sizeof(double) * 3 * n);
+#pragma omp for schedule(static)
+            for (int64_t p = 0; p < np; ++p) {
+                if (hit[p]) {
+                    orc_deposit_move(g, sgn[species[p]], &xold[3 * p], &xwall[3 * p], Jm);
+                    orc_deposit_move(g, sgn[species[p]], &xwall[3 * p], &x[3 * p], Jm);
+                } else {
+                    orc_deposit_move(g, sgn[species[p]], &xold[3 * p], &x[3 * p], Jm);
+                }
+            }
+        }
+        /* the per-thread currents added in thread order */
+#pragma omp parallel for schedule(static)
+        for (int64_t q = 0; q < 3 * n; ++q) {
+            double v = 0.0;
+            for (int t = 0; t < nthr; ++t) v += Jt[(size_t)t * 3 * n + q];
+            J[q] = v;
+        }
+#else
         for (int64_t p = 0; p < np; ++p) {
             if (hit[p]) {
                 orc_deposit_move(g, sgn[species[p]], &xold[3 * p], &xwall[3 * p], J);
@@ -538,6 +577,7 @@ void orc_step(const int g[3], double dt, double alpha0, int nsp,
                 orc_deposit_move(g, sgn[species[p]], &xold[3 * p], &x[3 * p], J);
             }
         }
+#endif
         /* 10. optional smoothing of the current (App. A.3.4) */
         if (filter) orc_filter27(g, 3, J);
         /* 12. e += alpha0 * sum_s sgn_s dV  (App. A.2, eq. max2bis) */
@@ -545,10 +585,16 @@ void orc_step(const int g[3], double dt, double alpha0, int nsp,
             e[q] += alpha0 * J[q];
         if (wall >= 0) orc_wall_fields(g, wall, e, b);
         /* 8. periodic particle boundary */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
         for (int64_t p = 0; p < np; ++p)
             for (int a = 0; a < 3; ++a)
                 x[3 * p + a] = wrapd(x[3 * p + a], g[a]);
     }
+#ifdef _OPENMP
+    free(Jt);
+#endif
     free(hit);
     free(xwall);
     free(xold);
@@ -564,11 +610,26 @@ void orc_backward_half(const int g[3], double dt, const double *kq, int64_t np,
                        const int32_t *species, const double *x, double *u,
                        const double *e, const double *b0)
 {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int64_t p = 0; p < np; ++p) {
         double E[3], B[3];
         orc_gather(g, e, b0, &x[3 * p], E, B);
         orc_boris(kq[species[p]], -0.5 * dt, E, B, &u[3 * p]);
     }
+}
+
+/* threads used by the parallel build (n > 0 sets them); 1 without OpenMP */
+int orc_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------ diagnostics */
@@ -862,6 +923,9 @@ void orc_load_pairs(const int g[3], uint64_t seed, uint64_t stream, int64_t npai
 {
     double bA = gbA / sqrt(1.0 + gbA * gbA), bB = gbB / sqrt(1.0 + gbB * gbB);
     uint64_t key[2] = {seed, stream};
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int64_t p = 0; p < npairs; ++p) {
         uint64_t r0[4], r1[4], r2[4];
         uint64_t c0[4] = {(uint64_t)p, 0, 0, 0}, c1[4] = {(uint64_t)p, 1, 0, 0},

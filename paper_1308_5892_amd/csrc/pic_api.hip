@@ -72,6 +72,7 @@ static void carve(Bump &A, const pic_config *cfg, std::vector<BoxHost> &bh, std:
         D.hist = A.take<int64_t>((size_t)std::max(1, cfg->hist_bins) * kMaxSpecies);
         D.alpha0 = 2.0 / (H.cfg.n_x * H.cfg.n_x * H.cfg.rho0);
         D.wall = H.cfg.walls - 1;
+        D.faraday4 = (cfg->flags & PIC_FARADAY4) != 0;
         for (int s = 0; s < kMaxSpecies; ++s) {
             SpeciesDev<R> &S = D.sp[s];
             memset(&S, 0, sizeof(S));
@@ -118,7 +119,7 @@ static int validate(const pic_config *cfg, std::vector<BoxHost> &bh, std::string
         }
     }
     if (!(cfg->dt > 0)) { err = "dt must be positive"; return PIC_EINVAL; }
-    if (cfg->flags & ~(uint32_t)(PIC_FP64_FORM | PIC_TRACK_IDS | PIC_FILTER_CURRENT)) {
+    if (cfg->flags & ~(uint32_t)(PIC_FP64_FORM | PIC_TRACK_IDS | PIC_FILTER_CURRENT | PIC_FARADAY4)) {
         err = "unknown flag";
         return PIC_EINVAL;
     }
@@ -147,6 +148,11 @@ static int validate(const pic_config *cfg, std::vector<BoxHost> &bh, std::string
         if (H.cfg.walls && H.cfg.n[H.cfg.walls - 1] < 2) { err = "walls need two cells along their axis"; return PIC_EINVAL; }
         if (H.cfg.walls && (cfg->flags & PIC_FILTER_CURRENT)) {
             err = "current smoothing is not available with walls";
+            return PIC_EINVAL;
+        }
+        if (H.cfg.walls && (cfg->flags & PIC_FARADAY4)) {
+            // its curl reaches two cells out, across the wall plane
+            err = "the fourth-order solver is not available with walls";
             return PIC_EINVAL;
         }
         H.nc = (int64_t)H.cfg.n[0] * H.cfg.n[1] * H.cfg.n[2];
@@ -192,7 +198,7 @@ static void make_layout(const pic_config *cfg, std::vector<BoxHost> &bh, char *b
         L.n_cblocks += (int)((H.nc + kBlock - 1) / kBlock);
         for (int s = 0; s < cfg->n_species; ++s) L.max_sitems += (H.stage_cap[s] + kBlock - 1) / kBlock;
     }
-    L.items_push = A.take<Item>(L.n_items);
+    L.items_push = A.take<Item>(8 * (size_t)L.n_items);   // room for the padding of the push order
     L.items_box = A.take<Item>(L.n_items);
     L.cblocks = A.take<CellBlock>(L.n_cblocks);
     L.sitems = A.take<StageItem>(std::max(1, L.max_sitems));
@@ -231,7 +237,10 @@ struct pic_ctx {
     std::vector<int> box_item_off;          // first item of each box in items_box
     std::vector<int> box_cblock_off;        // first cell block of each box
     std::vector<std::vector<int32_t>> stage_n, stage_half, next_id;
-    std::vector<std::vector<int64_t>> binned;   // particles binned per (box, species), for the capacity check
+    std::vector<std::vector<int64_t>> binned;   // particles binned per (box, species): capacity and push order
+    std::vector<Item> items;                // work items in box order (host copy)
+    std::vector<Item> push_perm;            // the push order uploaded last (host copy, kept for the copy)
+    int n_push = 0;                         // blocks of a push launch
     int cur = 0;
     int64_t step = 0;
     size_t lds_bytes = 0;
@@ -325,6 +334,67 @@ static StepConst<R> step_const(pic_ctx *ctx)
     return C;
 }
 
+// Push order of the work items.  The items (per box its tiles, then its
+// overflow sweeps, boxes in order) are cut into 8 runs of equal cost, one per
+// XCD: blocks go round-robin over the 8 XCDs of the MI355X, so block b runs
+// item (b / 8) of run (b % 8), and a box's neighbouring tiles meet in one L2.
+// A tile costs its share of the box's particles plus a fixed set-up worth
+// kTileCost particles; the cut falls on tile boundaries, so the runs differ by
+// less than one tile.  Within a run the boxes go in decreasing cost per tile
+// (the longest blocks first, so the run does not end on a long one), each box
+// with its tiles in order and its sweeps last.  Runs of unequal length are
+// padded with idle items (box -1).
+constexpr double kTileCost = 256.0;
+
+static void push_order(const pic_ctx *ctx, const std::vector<Item> &items, std::vector<Item> &perm)
+{
+    const int X = 8;
+    const int n = (int)items.size();
+    std::vector<double> per_tile(ctx->cfg.n_boxes);
+    for (int b = 0; b < ctx->cfg.n_boxes; ++b) {
+        double np = 0;
+        for (int s = 0; s < ctx->cfg.n_species; ++s) np += (double)ctx->binned[b][s];
+        per_tile[b] = np / ctx->bh[b].ntiles + kTileCost;
+    }
+    double total = 0;
+    for (const Item &it : items) total += it.tile >= 0 ? per_tile[it.box] : 0.0;
+    // runs: [cut[x], cut[x+1]); a cut goes after the tile that reaches x/X of
+    // the total, and after that box's sweeps when the tile is the box's last
+    std::vector<int> cut(X + 1, n);
+    cut[0] = 0;
+    double acc = 0;
+    for (int i = 0, x = 1; i < n && x < X; ++i) {
+        if (items[i].tile < 0) continue;
+        acc += per_tile[items[i].box];
+        if (acc >= total * x / X) {
+            int j = i + 1;
+            while (j < n && items[j].tile < 0 && items[j].box == items[i].box) ++j;
+            while (x < X && acc >= total * x / X) cut[x++] = j;
+        }
+    }
+    std::vector<std::vector<Item>> run(X);
+    size_t longest = 0;
+    for (int x = 0; x < X; ++x) {
+        // the run's boxes (or box parts) in decreasing cost per tile
+        std::vector<std::pair<int, int>> parts;   // [first item, end) of one box
+        for (int i = cut[x]; i < cut[x + 1];) {
+            int j = i;
+            while (j < cut[x + 1] && items[j].box == items[i].box) ++j;
+            parts.push_back({i, j});
+            i = j;
+        }
+        std::stable_sort(parts.begin(), parts.end(), [&](const std::pair<int, int> &a, const std::pair<int, int> &b) {
+            return per_tile[items[a.first].box] > per_tile[items[b.first].box];
+        });
+        for (auto &pr : parts)
+            for (int i = pr.first; i < pr.second; ++i) run[x].push_back(items[i]);
+        longest = std::max(longest, run[x].size());
+    }
+    perm.assign(longest * X, Item{-1, 0});
+    for (int x = 0; x < X; ++x)
+        for (size_t q = 0; q < run[x].size(); ++q) perm[q * X + x] = run[x][q];
+}
+
 // bin staged particles (and refresh the layout of the binned ones)
 template <typename R>
 static int merge_t(pic_ctx *ctx, bool force)
@@ -346,6 +416,13 @@ static int merge_t(pic_ctx *ctx, bool force)
     ctx->cur ^= 1;
     for (int b = 0; b < ctx->cfg.n_boxes; ++b)
         for (int s = 0; s < ctx->cfg.n_species; ++s) ctx->binned[b][s] += ctx->stage_n[b][s];
+    if (!si.empty()) {
+        // the boxes' particle counts changed: balance the push order again
+        push_order(ctx, ctx->items, ctx->push_perm);
+        HIPCHK(hipMemcpyAsync(ctx->L.items_push, ctx->push_perm.data(), ctx->push_perm.size() * sizeof(Item),
+                              hipMemcpyHostToDevice, ctx->stream));
+        ctx->n_push = (int)ctx->push_perm.size();
+    }
     for (auto &v : ctx->stage_n) std::fill(v.begin(), v.end(), 0);
     ctx->pending = false;
     if (!si.empty()) HIPCHK(hipStreamSynchronize(ctx->stream));   // the host stage list must outlive the copy
@@ -364,14 +441,8 @@ static int init_t(pic_ctx *ctx)
     make_layout<R>(&ctx->cfg, ctx->bh, ctx->arena, ctx->L, bd);
     HIPCHK(hipMemsetAsync(ctx->arena, 0, ctx->L.bytes - 256, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->L.boxes, bd.data(), bd.size() * sizeof(BoxDev<R>), hipMemcpyHostToDevice, ctx->stream));
-    // work items: per box its tiles then its overflow sweeps (box order), and
-    // the push order: the same list cut into 8 chunks of equal tile counts
-    // (a box's sweeps stay with its last tiles), dealt so that XCD x runs chunk
-    // x (blocks go round-robin over the 8 XCDs of the MI355X) and neighbouring
-    // tiles meet in one L2.  Chunks cut by item count instead would be shifted
-    // by the sweeps: with 4096 tiles, 7 XCDs would get 514, two more than 4
-    // full rounds of their 128 block slots, and those two would run alone at
-    // the end.
+    // work items: per box its tiles then its overflow sweeps (box order); the
+    // push order (push_order) is balanced again whenever particles are binned
     std::vector<Item> items;
     std::vector<CellBlock> cbs;
     for (int b = 0; b < ctx->cfg.n_boxes; ++b) {
@@ -384,37 +455,12 @@ static int init_t(pic_ctx *ctx)
     ctx->box_item_off.push_back((int)items.size());
     ctx->box_cblock_off.push_back((int)cbs.size());
     const int n = (int)items.size();
-    std::vector<Item> perm(n);
-    {
-        const int X = 8;
-        int nt = 0;
-        for (const Item &it : items) nt += it.tile >= 0;
-        const int per = (nt + X - 1) / X;
-        // chunk x: items [cut[x], cut[x + 1])
-        std::vector<int> cut(X + 1, n);
-        cut[0] = 0;
-        for (int i = 0, tiles = 0, x = 1; i < n && x < X; ++i) {
-            if (items[i].tile >= 0 && ++tiles == per * x) cut[x++] = i + 1;
-        }
-        std::vector<int> next(cut.begin(), cut.end() - 1);
-        std::vector<int> used(n, 0);
-        int g = 0;
-        for (int blk = 0; blk < n; ++blk) {
-            // block blk runs on XCD blk % 8: the next item of that chunk, or
-            // (chunk done) the first item not yet dealt
-            const int x = blk % X;
-            while (next[x] < cut[x + 1] && used[next[x]]) ++next[x];
-            int src = next[x] < cut[x + 1] ? next[x]++ : -1;
-            if (src < 0) {
-                while (used[g]) ++g;
-                src = g;
-            }
-            used[src] = 1;
-            perm[blk] = items[src];
-        }
-    }
+    ctx->items = items;
+    push_order(ctx, items, ctx->push_perm);
+    ctx->n_push = (int)ctx->push_perm.size();
     HIPCHK(hipMemcpyAsync(ctx->L.items_box, items.data(), n * sizeof(Item), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(hipMemcpyAsync(ctx->L.items_push, perm.data(), n * sizeof(Item), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->L.items_push, ctx->push_perm.data(), ctx->push_perm.size() * sizeof(Item),
+                          hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->L.cblocks, cbs.data(), cbs.size() * sizeof(CellBlock), hipMemcpyHostToDevice,
                           ctx->stream));
     size_t lds = 0;
@@ -462,8 +508,11 @@ int pic_init(const pic_config *cfg, void *dev_arena, size_t bytes, void *hip_str
     std::string err;
     int rc = validate(cfg, ctx->bh, err);
     if (rc) { delete ctx; return rc; }
-    // stability (App. B): Courant for the 3-D Yee scheme, and omega_pe dt < 2
-    if (!(cfg->dt < 1.0 / std::sqrt(3.0))) { delete ctx; return PIC_ECOURANT; }
+    // stability (App. B): Courant for the 3-D Yee scheme, and omega_pe dt < 2;
+    // with the fourth-order Faraday curl the largest mode has (dt/2)^2 sum_a
+    // (4 + 2/3) < 1, i.e. dt < 2/sqrt(14)
+    const double dt_max = (cfg->flags & PIC_FARADAY4) ? 2.0 / std::sqrt(14.0) : 1.0 / std::sqrt(3.0);
+    if (!(cfg->dt < dt_max)) { delete ctx; return PIC_ECOURANT; }
     for (auto &H : ctx->bh)
         if (!(cfg->dt / H.cfg.n_x < 2.0)) { delete ctx; return PIC_ECOURANT; }
     size_t need = 0;
@@ -578,8 +627,8 @@ static int step_t(pic_ctx *ctx, int n)
         }
         StepConst<R> C = step_const<R>(ctx);
         mark(ctx, 0, true);
-        HIPCHK(launch_push<R>(boxes, ctx->L.items_push, ctx->L.n_items, ctx->lds_bytes, C, ctx->fixed444 ? 1 : 0,
-                              ctx->walls ? 1 : 0, ctx->stream));
+        HIPCHK(launch_push<R>(boxes, ctx->L.items_push, ctx->n_push, ctx->lds_bytes, C, ctx->fixed444 ? 1 : 0,
+                              ctx->walls ? 1 : 0, (ctx->cfg.flags & PIC_FARADAY4) ? 1 : 0, ctx->stream));
         mark(ctx, 0, false);
         mark(ctx, 1, true);
         // the b update's last block also takes the overflow watch of the copy

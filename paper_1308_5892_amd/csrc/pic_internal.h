@@ -94,6 +94,7 @@ struct BoxDev {
     PIC_GLOBAL int64_t *hist;      // n_species * hist_bins
     double alpha0;                 // 2 / (n_x^2 rho0)
     int32_t wall;                  // axis with conducting walls, -1: periodic
+    int32_t faraday4;              // fourth-order curl of e in Faraday's law
     SpeciesDev<R> sp[kMaxSpecies];
 };
 
@@ -117,7 +118,8 @@ constexpr int kAccField = 0;       // [0..2] sum e^2/2, [3..5] sum (b^t)^2/2, [6
 constexpr int kAccSp = 8;          // then per species 6: K, P[3], count, sum(gamma-1)
 constexpr int kAccLen = kAccSp + 6 * kMaxSpecies;
 
-// work item of the particle kernels: box, and tile (>= 0) or -1-k for overflow block k
+// work item of the particle kernels: box, and tile (>= 0) or -1-k for overflow
+// block k; box -1 is an idle item (padding of the push order)
 struct Item {
     int32_t box;
     int32_t tile;
@@ -186,7 +188,7 @@ constexpr size_t kDiagScratchBytes = size_t(32) << 20;
 template <typename R> size_t push_lds_bytes(int t0, int t1, int t2);
 template <typename R>
 hipError_t launch_push(const BoxDev<R> *boxes, const Item *items, int nitems, size_t lds, const StepConst<R> &C,
-                       int fixed444, int walls, hipStream_t st);
+                       int fixed444, int walls, int faraday4, hipStream_t st);
 template <typename R>
 hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R dt, int nsp, int filter,
                          int clear_copy, int nboxes, uint32_t *watch, hipStream_t st);

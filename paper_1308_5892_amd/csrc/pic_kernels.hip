@@ -79,10 +79,38 @@ __device__ inline R fld(const PIC_GLOBAL R *F, const BoxDev<R> &B, int c, int i,
     return F[c * B.nc + i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)];
 }
 
-// b^t = b^{t-dt/2} - (dt/2) curl e^t at the b_c position of cell (i,j,k)
+// Fourth-order field solver (App. A.3.2, last paragraph; App. B, third item;
+// READING: the paper prints no stencil): Faraday's law takes the staggered
+// fourth-order difference along each axis, (9/8)(f[+1/2] - f[-1/2]) -
+// (1/24)(f[+3/2] - f[-3/2]); Ampere's law keeps the second-order curl, so the
+// second-order divergence of e still changes only by the charge-conserving
+// current (Gauss's law as with Yee).  d4_e: that difference along axis a of
+// component f of e at the point half a cell above (i,j,k) along a.
 template <typename R>
+__device__ inline R d4_e(const BoxDev<R> &B, int f, int i, int j, int k, int a)
+{
+    const int o0 = a == 0, o1 = a == 1, o2 = a == 2;
+    const R near = fld(B.e, B, f, i + o0, j + o1, k + o2) - fld(B.e, B, f, i, j, k);
+    const R far = fld(B.e, B, f, i + 2 * o0, j + 2 * o1, k + 2 * o2) - fld(B.e, B, f, i - o0, j - o1, k - o2);
+    return R(9.0 / 8.0) * near - R(1.0 / 24.0) * far;
+}
+
+// (curl e)_c of the fourth-order solver at the b_c position of cell (i,j,k)
+template <typename R>
+__device__ inline R curl4_e(const BoxDev<R> &B, int c, int i, int j, int k)
+{
+    if (c == 0) return d4_e(B, 2, i, j, k, 1) - d4_e(B, 1, i, j, k, 2);
+    if (c == 1) return d4_e(B, 0, i, j, k, 2) - d4_e(B, 2, i, j, k, 0);
+    return d4_e(B, 1, i, j, k, 0) - d4_e(B, 0, i, j, k, 1);
+}
+
+// b^t = b^{t-dt/2} - (dt/2) curl e^t at the b_c position of cell (i,j,k).
+// F4: 1 the fourth-order curl, 0 Yee's, -1 as the box says (the push kernel
+// is compiled for one solver, so its loop carries only that one's code).
+template <typename R, int F4 = -1>
 __device__ inline R bt_global(const BoxDev<R> &B, int c, int i, int j, int k, R hdt)
 {
+    if (F4 == 1 || (F4 < 0 && B.faraday4)) return fld(B.b, B, c, i, j, k) - hdt * curl4_e(B, c, i, j, k);
     const PIC_GLOBAL R *e = B.e;
     R curl;
     if (c == 0)
@@ -103,19 +131,19 @@ template <typename R>
 __device__ inline R node_avg4(R a, R b, R c, R d) { return R(0.25) * (a + b + c + d); }
 
 // Component c (0-2: e, 3-5: b^t) at node (i,j,k), read from HBM.
-template <typename R>
+template <typename R, int F4 = -1>
 __device__ inline R node_value_global(const BoxDev<R> &B, int c, int i, int j, int k, R hdt)
 {
     switch (c) {
     case 0: return node_avg2(fld(B.e, B, 0, i - 1, j, k), fld(B.e, B, 0, i, j, k));
     case 1: return node_avg2(fld(B.e, B, 1, i, j - 1, k), fld(B.e, B, 1, i, j, k));
     case 2: return node_avg2(fld(B.e, B, 2, i, j, k - 1), fld(B.e, B, 2, i, j, k));
-    case 3: return node_avg4(bt_global(B, 0, i, j, k, hdt), bt_global(B, 0, i, j - 1, k, hdt),
-                             bt_global(B, 0, i, j - 1, k - 1, hdt), bt_global(B, 0, i, j, k - 1, hdt));
-    case 4: return node_avg4(bt_global(B, 1, i, j, k, hdt), bt_global(B, 1, i, j, k - 1, hdt),
-                             bt_global(B, 1, i - 1, j, k - 1, hdt), bt_global(B, 1, i - 1, j, k, hdt));
-    default: return node_avg4(bt_global(B, 2, i, j, k, hdt), bt_global(B, 2, i - 1, j, k, hdt),
-                              bt_global(B, 2, i - 1, j - 1, k, hdt), bt_global(B, 2, i, j - 1, k, hdt));
+    case 3: return node_avg4(bt_global<R, F4>(B, 0, i, j, k, hdt), bt_global<R, F4>(B, 0, i, j - 1, k, hdt),
+                             bt_global<R, F4>(B, 0, i, j - 1, k - 1, hdt), bt_global<R, F4>(B, 0, i, j, k - 1, hdt));
+    case 4: return node_avg4(bt_global<R, F4>(B, 1, i, j, k, hdt), bt_global<R, F4>(B, 1, i, j, k - 1, hdt),
+                             bt_global<R, F4>(B, 1, i - 1, j, k - 1, hdt), bt_global<R, F4>(B, 1, i - 1, j, k, hdt));
+    default: return node_avg4(bt_global<R, F4>(B, 2, i, j, k, hdt), bt_global<R, F4>(B, 2, i - 1, j, k, hdt),
+                              bt_global<R, F4>(B, 2, i - 1, j - 1, k, hdt), bt_global<R, F4>(B, 2, i, j - 1, k, hdt));
     }
 }
 
@@ -148,7 +176,7 @@ __device__ inline R trilinear_eval(P k8, const R d[3], R pxy, R pyz, R pzx, R px
 
 // e^t and b^t at (cell, d) from HBM: the node values, the interpolant's
 // coefficients and its value, as the tile path computes them.
-template <typename R>
+template <typename R, int F4 = -1>
 __device__ inline void gather_global(const BoxDev<R> &B, int ix, int iy, int iz, const R d[3], R hdt,
                                      R E[3], R Bf[3])
 {
@@ -156,7 +184,7 @@ __device__ inline void gather_global(const BoxDev<R> &B, int ix, int iy, int iz,
     for (int c = 0; c < 6; ++c) {
         R f[8], cf[8];
         for (int q = 0; q < 8; ++q)
-            f[q] = node_value_global(B, c, ix + (q & 1), iy + ((q >> 1) & 1), iz + (q >> 2), hdt);
+            f[q] = node_value_global<R, F4>(B, c, ix + (q & 1), iy + ((q >> 1) & 1), iz + (q >> 2), hdt);
         trilinear_coef(f, cf);
         const R v = trilinear_eval(cf, d, pxy, pyz, pzx, pxyz);
         if (c < 3) E[c] = v;
@@ -285,19 +313,20 @@ __device__ inline TileRanges overflow_range(const BoxDev<R> &B, const SpeciesDev
     return r;
 }
 
+// Offset of x in its cell, x - floor(x), kept below 1: an x a hair below a
+// node plane, whose difference would round up to 1, stays in the lower cell
+// at the largest offset below 1 (one v_fract_f32, which clamps so).
+__device__ inline float offset_in_cell(float x) { return __builtin_amdgcn_fractf(x); }
+__device__ inline double offset_in_cell(double x) { return fmin(x - floor(x), 1.0 - 0x1p-53); }
+
 // New cell and offset after the move x1 = d + D (home-cell frame), wrapped.
 template <typename R>
 __device__ inline int32_t advance_cell(const BoxDev<R> &B, int ix, int iy, int iz, const R x1[3], R dn[3])
 {
     int c[3] = {ix, iy, iz};
     for (int a = 0; a < 3; ++a) {
-        int f = x1[a] < R(0) ? -1 : (x1[a] >= R(1) ? 1 : 0);
-        R v = x1[a] - R(f);
-        if (v >= R(1)) {        // x1 a hair below 0: rounds to the cell boundary
-            v = R(0);
-            f += 1;
-        }
-        dn[a] = v;
+        const int f = (int)floor(x1[a]);      // -1, 0 or 1: x1 lies in (-1, 2)
+        dn[a] = offset_in_cell(x1[a]);
         int ci = c[a] + f;
         if (ci < 0) ci += B.n[a];
         else if (ci >= B.n[a]) ci -= B.n[a];
@@ -360,7 +389,8 @@ __host__ __device__ inline size_t queue_bytes()
 // first holds the staged raw fields and node fields and then the tile current.
 // Values per cell in the gather's coefficient table: 8 per field component,
 // padded from 48 to 52 so that the 16-byte reads of lanes in different cells
-// start on different LDS banks.
+// start on different LDS banks.  (A coefficient-major table, one dword per
+// lane per read, ran the push 43 % slower.)
 constexpr int kCoef = 52;
 
 // LDS of one push block for tiles of t0 x t1 x t2 cells, three regions:
@@ -504,24 +534,22 @@ __device__ inline void wall_rest_start(int w, R P[3], int s[3])
     }
 }
 
-// Point where axis `ax` meets its plane (parameter l): that coordinate is the
-// plane itself, every other coordinate stays on its own side of its plane
-// (the far side once its own crossing parameter is <= l).
+__device__ inline float clamp01(float v) { return __builtin_amdgcn_fmed3f(v, 0.0f, 1.0f); }
+__device__ inline double clamp01(double v) { return fmin(fmax(v, 0.0), 1.0); }
+
+// First breakpoint of a move d -> d + D: where its first crossing axis ax
+// meets its plane (parameter l).  That coordinate is the plane itself; no
+// other plane is crossed before it, so every other coordinate lies in the
+// closed home cell [0, 1] (clamped there against rounding).  A plane crossed
+// at the same parameter is left at the plane: its own piece then has length
+// zero.
 template <typename R>
-__device__ inline void crossing_point(const R d[3], const R D[3], const int dir[3], const R lam[3], int ax, R l,
-                                      R q[3])
+__device__ inline void first_breakpoint(const R d[3], const R D[3], const int dir[3], int ax, R l, R q[3])
 {
-    // branch-free: both clamps are formed and one is selected, so a wave
-    // whose lanes cross in different directions runs one straight sequence
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const R v = fma(l, D[a], d[a]);
-        const R pl = dir[a] > 0 ? R(1) : R(0);
-        // the side of the plane to keep: above it (max) when the axis moves
-        // up and is crossed, or moves down and is not crossed yet
-        const bool above = (dir[a] > 0) == (lam[a] <= l);
-        const R c = above ? fmax(v, pl) : fmin(v, pl);
-        q[a] = a == ax ? pl : (dir[a] != 0 ? c : v);
+        const R c = clamp01(fma(l, D[a], d[a]));
+        q[a] = a == ax ? (dir[a] > 0 ? R(1) : R(0)) : c;
     }
 }
 
@@ -560,7 +588,7 @@ __device__ inline void chain_point(const R ps[3], const R x1[3], int meta, int k
         const bool far = (crossed >> a) & 1;
         const R v = fma(l, Dp[a], ps[a]);
         const R pl = da > 0 ? R(1) : R(0);
-        // branch-free, as in crossing_point: keep above the plane when the
+        // branch-free: keep above the plane when the
         // axis moves up and is crossed, or moves down and is not crossed yet
         const bool above = (da > 0) == far;
         const R c = above ? fmax(v, pl) : fmin(v, pl);
@@ -647,7 +675,7 @@ __device__ inline void deposit_move(const R d[3], const R D[3], R scale, Add &&a
     if (nb == 0) {
         p1[0] = x1[0]; p1[1] = x1[1]; p1[2] = x1[2];
     } else {
-        crossing_point(d, D, dir, lam, o0, l0, p1);
+        first_breakpoint(d, D, dir, o0, l0, p1);
     }
     const R dd[3] = {p1[0] - d[0], p1[1] - d[1], p1[2] - d[2]};
     piece_fluxes(d, dd, scale, [&](int a, int f, auto q) {
@@ -758,12 +786,12 @@ __device__ inline int move_bin(const TileGeom<R> &g, const TileRim &rim, const i
 template <typename R> struct PushWaves { static constexpr int value = 4; };
 template <> struct PushWaves<double> { static constexpr int value = 2; };
 
-template <typename R, int FIX, int WALLS>
+template <typename R, int FIX, int WALLS, int F4>
 __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const BoxDev<R> *__restrict__ boxes,
                                                       const Item *__restrict__ items, StepConst<R> C);
 
 // Overflow sweep: same physics, fields from HBM, current by global atomics.
-template <typename R, int WALLS>
+template <typename R, int WALLS, int F4>
 __device__ void push_overflow(const BoxDev<R> &B, int kblk, const StepConst<R> &C)
 {
     using JT = typename JType<R>::T;
@@ -789,7 +817,7 @@ __device__ void push_overflow(const BoxDev<R> &B, int kblk, const StepConst<R> &
             }
             const int ix = cell_x(cell), iy = cell_y(cell), iz = cell_z(cell);
             R E[3], Bf[3];
-            if (valid) gather_global(B, ix, iy, iz, d, hdt, E, Bf);
+            if (valid) gather_global<R, F4>(B, ix, iy, iz, d, hdt, E, Bf);
             else for (int a = 0; a < 3; ++a) { E[a] = R(0); Bf[a] = R(0); }
             R D[3];
             boris_move(hk, E, Bf, u, C.dt, valid, C.flags, D);
@@ -831,16 +859,17 @@ __device__ void push_overflow(const BoxDev<R> &B, int kblk, const StepConst<R> &
 // FP32 form: four waves per SIMD (at most 128 VGPRs), the occupancy that
 // hides the latency of the LDS gather and of the particle loads best on
 // gfx950.  FP64 form: two (its doubled registers would spill at four).
-template <typename R, int FIX, int WALLS>
+template <typename R, int FIX, int WALLS, int F4>
 __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const BoxDev<R> *__restrict__ boxes,
                                                       const Item *__restrict__ items, StepConst<R> C)
 {
     using JT = typename JType<R>::T;
     extern __shared__ __align__(16) unsigned char smem[];
     const Item it = items[blockIdx.x];
+    if (it.box < 0) return;                       // padding of the push order
     const BoxDev<R> &B = boxes[it.box];
     if (it.tile < 0) {
-        push_overflow<R, WALLS>(B, -1 - it.tile, C);
+        push_overflow<R, WALLS, F4>(B, -1 - it.tile, C);
         return;
     }
     const int T = it.tile;
@@ -923,7 +952,17 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
 
     // 2. b^t = b^{t-dt/2} - (dt/2) curl e^t (App. A.3.1 item 1), in place
     const R hdt = R(0.5) * C.dt;
-    {
+    if (F4) {
+        // the fourth-order curl reaches two cells out, past the staged halo:
+        // b^t from HBM, exactly as the HBM path forms it
+        for (int q = tid; q < g.BN; q += kBlock) {
+            const int jk = div_small(q, mBX), i = q - jk * BX;
+            const int k = div_small(jk, mBY), j = jk - k * g.BY;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                rb[c * g.BN + q] = bt_global<R, 1>(B, c, g.o[0] - 1 + i, g.o[1] - 1 + j, g.o[2] - 1 + k, hdt);
+        }
+    } else {
         const R *ex = re, *ey = re + g.JN, *ez = re + 2 * g.JN;
         for (int q = tid; q < g.BN; q += kBlock) {
             const int jk = div_small(q, mBX), i = q - jk * BX;
@@ -1092,7 +1131,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             // gather: the cell's trilinear interpolant at the in-cell offset
             R E[3] = {R(0), R(0), R(0)}, Bf[3] = {R(0), R(0), R(0)};
             if (!inside) {
-                gather_global(B, ix, iy, iz, d, hdt, E, Bf);
+                gather_global<R, F4>(B, ix, iy, iz, d, hdt, E, Bf);
             } else {
                 const R *cf = coef + __umul24(kCoef, lx | (ly << tsx) | (lz << tsxy));
                 const R pxy = d[0] * d[1], pyz = d[1] * d[2], pzx = d[2] * d[0], pxyz = pxy * d[2];
@@ -1137,13 +1176,8 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             R dn[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                int f = dir[a];
-                R v = x1[a] - R(f);
-                if (v >= R(1)) {        // x1 a hair below 0: rounds onto the cell boundary
-                    v = R(0);
-                    f += 1;
-                }
-                dn[a] = v;
+                const int f = dir[a];                 // floor(x1)
+                dn[a] = offset_in_cell(x1[a]);
                 lc[a] += f;
                 int ci = cn[a] + f;
                 if (edge[a] || anyout) ci = ci < 0 ? ci + bn[a] : (ci >= bn[a] ? ci - bn[a] : ci);
@@ -1209,7 +1243,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             if (nb == 0) {
                 p1[0] = x1[0]; p1[1] = x1[1]; p1[2] = x1[2];
             } else {
-                crossing_point(d, D, dir, lam, o0, l0, p1);
+                first_breakpoint(d, D, dir, o0, l0, p1);
             }
             if (valid && inside) {
                 const R dd[3] = {p1[0] - d[0], p1[1] - d[1], p1[2] - d[2]};
@@ -1372,9 +1406,16 @@ __global__ void __launch_bounds__(kBlock) advance_b_kernel(const BoxDev<R> *__re
     const int64_t sy = (j + 1 < n1) ? n0 : (int64_t)n0 * (1 - n1);
     const int64_t sz = (k + 1 < n2) ? (int64_t)n0 * n1 : (int64_t)n0 * n1 * (1 - n2);
     const R *ex = B.e, *ey = B.e + B.nc, *ez = B.e + 2 * B.nc;
-    const R cx = (ez[p + sy] - ez[p]) - (ey[p + sz] - ey[p]);
-    const R cy = (ex[p + sz] - ex[p]) - (ez[p + sx] - ez[p]);
-    const R cz = (ey[p + sx] - ey[p]) - (ex[p + sy] - ex[p]);
+    R cx, cy, cz;
+    if (B.faraday4) {
+        cx = curl4_e(B, 0, i, j, k);
+        cy = curl4_e(B, 1, i, j, k);
+        cz = curl4_e(B, 2, i, j, k);
+    } else {
+        cx = (ez[p + sy] - ez[p]) - (ey[p + sz] - ey[p]);
+        cy = (ex[p + sz] - ex[p]) - (ez[p + sx] - ez[p]);
+        cz = (ey[p + sx] - ey[p]) - (ex[p + sy] - ex[p]);
+    }
     B.b[p] -= h * cx;
     B.b[B.nc + p] -= h * cy;
     B.b[2 * B.nc + p] -= h * cz;
@@ -1855,11 +1896,11 @@ size_t push_lds_bytes(int t0, int t1, int t2) { return tile_lds_bytes<R>(t0, t1,
 
 template <typename R>
 hipError_t launch_push(const BoxDev<R> *boxes, const Item *items, int nitems, size_t lds, const StepConst<R> &C,
-                       int fixed444, int walls, hipStream_t st)
+                       int fixed444, int walls, int faraday4, hipStream_t st)
 {
     // dynamic LDS beyond 64 KiB has to be allowed per kernel: the limit each
     // variant was last raised to, raised again when a launch needs more
-    static size_t raised[4] = {65536, 65536, 65536, 65536};
+    static size_t raised[6] = {65536, 65536, 65536, 65536, 65536, 65536};
     auto go = [&](auto kern, int v) -> hipError_t {
         if (lds > raised[v]) {
             const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -1870,8 +1911,10 @@ hipError_t launch_push(const BoxDev<R> *boxes, const Item *items, int nitems, si
         hipLaunchKernelGGL(kern, dim3(nitems), dim3(kBlock), lds, st, boxes, items, C);
         return hipGetLastError();
     };
-    if (walls) return fixed444 ? go(push_kernel<R, 1, 1>, 3) : go(push_kernel<R, 0, 1>, 2);
-    return fixed444 ? go(push_kernel<R, 1, 0>, 1) : go(push_kernel<R, 0, 0>, 0);
+    // walls and the fourth-order solver are never combined (pic_plan refuses it)
+    if (walls) return fixed444 ? go(push_kernel<R, 1, 1, 0>, 3) : go(push_kernel<R, 0, 1, 0>, 2);
+    if (faraday4) return fixed444 ? go(push_kernel<R, 1, 0, 1>, 5) : go(push_kernel<R, 0, 0, 1>, 4);
+    return fixed444 ? go(push_kernel<R, 1, 0, 0>, 1) : go(push_kernel<R, 0, 0, 0>, 0);
 }
 
 template <typename R>
@@ -2085,7 +2128,7 @@ hipError_t launch_spectrum(const BoxDev<R> *boxes, int box, const int n[3], int 
 #define PIC_INSTANTIATE(R)                                                                                     \
     template size_t push_lds_bytes<R>(int, int, int);                                                         \
     template hipError_t launch_push<R>(const BoxDev<R> *, const Item *, int, size_t, const StepConst<R> &,   \
-                                       int, int, hipStream_t);                                                \
+                                       int, int, int, hipStream_t);                                           \
     template hipError_t launch_fields<R>(const BoxDev<R> *, const CellBlock *, int, R, int, int, int, int,     \
                                          uint32_t *, hipStream_t);                                                        \
     template hipError_t launch_advance_b<R>(const BoxDev<R> *, const CellBlock *, int, R, hipStream_t);       \

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libpic.so")
 
 MAX_SPECIES = 4
 PIC_OK, PIC_EINVAL, PIC_ECOURANT, PIC_ENOMEM, PIC_EDEVICE, PIC_EFLAG, PIC_ESTATE = 0, -1, -2, -3, -4, -5, -6
-PIC_FP64_FORM, PIC_TRACK_IDS, PIC_FILTER_CURRENT = 1, 2, 4
+PIC_FP64_FORM, PIC_TRACK_IDS, PIC_FILTER_CURRENT, PIC_FARADAY4 = 1, 2, 4, 8
 PIC_PROFILE_UNIFORM, PIC_PROFILE_HARRIS = 0, 1
 PIC_FLAG_NONFINITE, PIC_FLAG_LOST = 1, 2
 ERROR_NAMES = {0: "PIC_OK", -1: "PIC_EINVAL", -2: "PIC_ECOURANT", -3: "PIC_ENOMEM",
@@ -141,7 +141,7 @@ def _ptr(a):
 # ------------------------------------------------------------- ABI wrappers
 
 def make_config(boxes, species, dt, sort_interval=0, fp64=False, track_ids=False, hist_bins=0,
-                hist_lo=-4.0, hist_hi=3.0, headroom=0.0, filter_current=False):
+                hist_lo=-4.0, hist_hi=3.0, headroom=0.0, filter_current=False, faraday4=False):
     """Build a pic_config.  boxes: dicts with n, n_x, rho0, max_particles[, tile];
     species: list of (q_over_e, m_over_me)."""
     arr = (pic_box * len(boxes))()
@@ -163,7 +163,7 @@ def make_config(boxes, species, dt, sort_interval=0, fp64=False, track_ids=False
     cfg.dt = dt
     cfg.sort_interval = sort_interval
     cfg.flags = ((PIC_FP64_FORM if fp64 else 0) | (PIC_TRACK_IDS if track_ids else 0) |
-                 (PIC_FILTER_CURRENT if filter_current else 0))
+                 (PIC_FILTER_CURRENT if filter_current else 0) | (PIC_FARADAY4 if faraday4 else 0))
     cfg.hist_bins = hist_bins
     cfg.hist_lo = hist_lo
     cfg.hist_hi = hist_hi

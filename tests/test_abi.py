@@ -38,9 +38,9 @@ def test_every_declared_symbol_is_exported(P):
     assert sorted(P.EXPORTED) == names
 
 
-def _device_kernel_names(lib_path, tmp_path):
-    """Kernel symbols of every gfx950 code object in the library's fat binary
-    (each translation unit contributes one offload bundle)."""
+def _code_objects(lib_path, tmp_path):
+    """Paths of the gfx950 code objects in the library's fat binary (each
+    translation unit contributes one offload bundle)."""
     import struct
     llvm = "/opt/rocm/llvm/bin"
     blob = tmp_path / "fatbin.bin"
@@ -48,7 +48,7 @@ def _device_kernel_names(lib_path, tmp_path):
                            str(tmp_path / "copy.so")])
     data = blob.read_bytes()
     magic = b"__CLANG_OFFLOAD_BUNDLE__"
-    names, start, k = set(), data.find(magic), 0
+    out, start = [], data.find(magic)
     while start >= 0:
         n = struct.unpack_from("<Q", data, start + len(magic))[0]
         pos = start + len(magic) + 8
@@ -57,14 +57,42 @@ def _device_kernel_names(lib_path, tmp_path):
             triple = data[pos + 24:pos + 24 + tl].decode()
             pos += 24 + tl
             if "gfx950" in triple:
-                co = tmp_path / f"co{k}.o"
-                k += 1
+                co = tmp_path / f"co{len(out)}.o"
                 co.write_bytes(data[start + off:start + off + size])
-                out = subprocess.run([f"{llvm}/llvm-readelf", "--symbols", "-W", str(co)], capture_output=True,
-                                     text=True).stdout
-                names |= {m[:-3] for m in re.findall(r"\s(\S+\.kd)$", out, re.M)}
+                out.append(co)
         start = data.find(magic, start + 1)
-    return names, k
+    return out
+
+
+def test_push_kernels_keep_their_register_budget(P, tmp_path):
+    # the FP32 push kernels run 4 waves per SIMD: at most 128 VGPRs, and no
+    # VGPR spilled to scratch (a spill in the particle loop costs tens of
+    # per cent); the wall variants index a 16-byte per-lane array
+    meta = ""
+    for co in _code_objects(P.LIB_PATH, tmp_path):
+        meta += subprocess.run(["/opt/rocm/llvm/bin/llvm-readelf", "--notes", str(co)], capture_output=True,
+                               text=True).stdout
+    found = 0
+    for block in meta.split("  - .agpr_count:")[1:]:
+        name = re.search(r"\.name:\s+(\S+)", block).group(1)
+        if not name.startswith("_ZN3pic11push_kernelIf"):
+            continue
+        found += 1
+        vgpr = int(re.search(r"\.vgpr_count:\s+(\d+)", block).group(1))
+        spill = int(re.search(r"\.vgpr_spill_count:\s+(\d+)", block).group(1))
+        priv = int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", block).group(1))
+        assert vgpr <= 128 and spill == 0 and priv <= 16, (name, vgpr, spill, priv)
+    assert found == 6
+
+
+def _device_kernel_names(lib_path, tmp_path):
+    """Kernel symbols of every gfx950 code object in the library."""
+    names, cos = set(), _code_objects(lib_path, tmp_path)
+    for co in cos:
+        out = subprocess.run(["/opt/rocm/llvm/bin/llvm-readelf", "--symbols", "-W", str(co)], capture_output=True,
+                             text=True).stdout
+        names |= {m[:-3] for m in re.findall(r"\s(\S+\.kd)$", out, re.M)}
+    return names, len(cos)
 
 
 def test_every_host_kernel_has_its_device_code(P, tmp_path):
@@ -148,6 +176,18 @@ def test_plan_rejects_bad_config(P, bad):
     with pytest.raises(P.PicError) as ei:
         P.pic_plan(_cfg(P, **bad))
     assert ei.value.code == P.PIC_EINVAL
+
+
+def test_fourth_order_solver_flag(P):
+    # accepted on periodic boxes, refused with walls (its curl reaches across
+    # the wall plane), and its own Courant bound dt < 2/sqrt(14) = 0.5345
+    assert P.pic_plan(_cfg(P, faraday4=True)) > 0
+    with pytest.raises(P.PicError) as ei:
+        P.pic_plan(_cfg(P, faraday4=True, box={"walls": 2}))
+    assert ei.value.code == P.PIC_EINVAL
+    ctx = C.c_void_p()
+    cfg = _cfg(P, dt=0.54, faraday4=True)       # below Yee's 0.577, above 0.5345
+    assert P.lib().pic_init(C.byref(cfg), C.c_void_p(256), 1 << 40, None, C.byref(ctx)) == P.PIC_ECOURANT
 
 
 def test_plan_rejects_unknown_flag(P):

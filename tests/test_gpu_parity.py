@@ -598,3 +598,76 @@ def test_fp64_tiles_needing_more_lds_in_one_process():
             assert G.u_rel_err(u, st.u[st.species == sp], 1e-3).max() < 1e-11, tile
         assert s.diag(0)["flags"] == 0
         s.close()
+
+
+# ------------------------------------------ fourth-order solver (PIC_FARADAY4)
+
+@pytest.mark.parametrize("fp64,tol", [(False, 2e-5), (True, 1e-12)])
+def test_fourth_order_solver_vacuum_fields_match_oracle(fp64, tol):
+    # random e and b (every wave number) in vacuum, 20 steps: the fourth-order
+    # Faraday curl and Yee's Ampere curl against the oracle's
+    rng = np.random.default_rng(51)
+    dims = (10, 12, 7)
+    n = int(np.prod(dims))
+    e0, b0 = G.random_fields(rng, n, 0.3, 0.3)
+    s = G.sim(dims, 10.0, 2.0, [1, 1], fp64=fp64, faraday4=True)
+    st = G.oracle_state(dims, 10.0, 2.0)
+    st.faraday4 = True
+    G.start(s, st, [], e=e0, b=b0, fp64=fp64)
+    s.step(20)
+    st.step(20)
+    e, b, _ = s.fields(0)
+    assert np.max(np.abs(e - st.e)) < tol * np.abs(st.e).max()
+    assert np.max(np.abs(b - st.b)) < tol * np.abs(st.b).max()
+    s.close()
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+@pytest.mark.parametrize("dims", [(9, 8, 6), (12, 12, 12)])
+def test_fourth_order_solver_one_step_on_frozen_fields(fp64, dims):
+    # random particles in random fields: the gather at x^t uses b^t formed
+    # with the fourth-order curl (in the tile and on the HBM path)
+    rng = np.random.default_rng(43)
+    n = 3000
+    s = G.sim(dims, 10.0, 40.0, [n, n], fp64=fp64, faraday4=True)
+    st = G.oracle_state(dims, 10.0, 40.0)
+    st.faraday4 = True
+    e, b = G.random_fields(rng, int(np.prod(dims)), 0.05, 0.3)
+    G.start(s, st, [_random_particles(rng, dims, n) for _ in range(2)], e=e, b=b, fp64=fp64)
+    s.step(1)
+    st.step(1)
+    tol = 1e-12 if fp64 else 2e-6
+    for sp in range(2):
+        x, u, _ = s.particles(0, sp)
+        assert G.u_rel_err(u, st.u[st.species == sp], 1e-3).max() < tol
+        assert np.abs(G.wrap_delta(x, st.x[st.species == sp], dims)).max() < tol
+    e1, b1, _ = s.fields(0)
+    assert np.max(np.abs(b1 - st.b)) < tol * np.abs(st.b).max()
+    assert np.max(np.abs(e1 - st.e)) < tol * np.abs(st.e).max()
+    s.close()
+
+
+@pytest.mark.parametrize("fp64,tol", [(False, 1e-5), (True, 1e-11)])
+def test_fourth_order_solver_thermal_ten_steps(fp64, tol):
+    # a hot pair plasma (theta = 0.3) for 10 steps: per-particle momenta,
+    # fields and the FP64 Gauss residual
+    dims, ppc = (12, 10, 8), 6
+    npairs = ppc * int(np.prod(dims))
+    s = G.sim(dims, 10.0, 2 * ppc, [npairs, npairs], fp64=fp64, faraday4=True)
+    st = G.oracle_state(dims, 10.0, 2 * ppc)
+    st.faraday4 = True
+    mj = {"theta": 0.3, "gb": 0.0, "axis": 1}
+    parts = G.oracle_loaded(dims, 0.5, 10.0, 2 * ppc, G.PAIR, [dict(seed=7, stream=0, npairs=npairs, A=mj, B=mj)])
+    G.start(s, st, parts, fp64=fp64)
+    s.step(10)
+    st.step(10)
+    for sp in range(2):
+        _, u, _ = s.particles(0, sp)
+        assert G.u_rel_err(u, st.u[st.species == sp], 1e-2).max() < tol
+    e, b, _ = s.fields(0)
+    assert np.max(np.abs(e - st.e)) < (1e-11 if fp64 else 1e-4) * np.abs(st.e).max()
+    d = s.diag(0)
+    assert d["flags"] == 0
+    if fp64:
+        assert d["gauss_max"] < 1e-13
+    s.close()

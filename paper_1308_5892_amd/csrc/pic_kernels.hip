@@ -150,9 +150,10 @@ __device__ inline R node_value_global(const BoxDev<R> &B, int c, int i, int j, i
 // The trilinear interpolant of the eight node values of a cell, f[q] at node
 // (q & 1, (q >> 1) & 1, q >> 2), written as c0 + c1 x + c2 y + c3 z + c4 xy +
 // c5 yz + c6 zx + c7 xyz in the in-cell offsets: its coefficients, and its
-// value at d (pxy = d0 d1, pyz = d1 d2, pzx = d2 d0, pxyz = d0 d1 d2).  The
-// tile path and the HBM path both use these two, so the fields a particle
-// sees do not depend on the path it takes.
+// value at d, nested as c0 + x (c1 + y (c4 + z c7) + z c6) + y (c2 + z c5) +
+// z c3 (seven multiply-adds, no products of the offsets).  The tile path and
+// the HBM path both use these two, so the fields a particle sees do not
+// depend on the path it takes.
 template <typename R, typename P>
 __device__ inline void trilinear_coef(const R f[8], P cf)
 {
@@ -168,10 +169,12 @@ __device__ inline void trilinear_coef(const R f[8], P cf)
     cf[7] = ((f[7] - f[6]) - (f[5] - f[4])) - axy;
 }
 template <typename R, typename P>
-__device__ inline R trilinear_eval(P k8, const R d[3], R pxy, R pyz, R pzx, R pxyz)
+__device__ inline R trilinear_eval(P k8, const R d[3])
 {
-    return k8[0] + d[0] * k8[1] + d[1] * k8[2] + d[2] * k8[3] + pxy * k8[4] + pyz * k8[5] + pzx * k8[6] +
-           pxyz * k8[7];
+    const R t = fma(d[2], k8[7], k8[4]);
+    const R u = fma(d[2], k8[6], fma(d[1], t, k8[1]));
+    const R v = fma(d[2], k8[5], k8[2]);
+    return fma(d[2], k8[3], fma(d[1], v, fma(d[0], u, k8[0])));
 }
 
 // e^t and b^t at (cell, d) from HBM: the node values, the interpolant's
@@ -180,13 +183,12 @@ template <typename R, int F4 = -1>
 __device__ inline void gather_global(const BoxDev<R> &B, int ix, int iy, int iz, const R d[3], R hdt,
                                      R E[3], R Bf[3])
 {
-    const R pxy = d[0] * d[1], pyz = d[1] * d[2], pzx = d[2] * d[0], pxyz = pxy * d[2];
     for (int c = 0; c < 6; ++c) {
         R f[8], cf[8];
         for (int q = 0; q < 8; ++q)
             f[q] = node_value_global<R, F4>(B, c, ix + (q & 1), iy + ((q >> 1) & 1), iz + (q >> 2), hdt);
         trilinear_coef(f, cf);
-        const R v = trilinear_eval(cf, d, pxy, pyz, pzx, pxyz);
+        const R v = trilinear_eval(cf, d);
         if (c < 3) E[c] = v;
         else Bf[c - 3] = v;
     }
@@ -562,55 +564,54 @@ __device__ inline int move_meta(int k, int nb, int o0, int o1, int o2, const int
            ((dir[2] + 1) << 14);
 }
 
-// Breakpoint of crossing k of a move, continued from the previous breakpoint
-// ps towards the move's end x1 (home-cell frame): the crossing axis sits on
-// its plane, an axis already crossed stays on the far side of its plane, one
-// still to cross on the near side.  Every later breakpoint of a move is
-// computed this way from the one before, on the tile path and on the HBM
-// path alike, so consecutive pieces share their breakpoints exactly and the
-// last piece ends exactly at the particle's new position.
+// Piece k of a queued move (0 <= k <= nb crossings), from its start ps (the
+// previous breakpoint; home-cell frame) towards the move's end x1.  The piece
+// lies in the cell offset `offc` from the home cell: the directions of the
+// crossings before it (axes o_0 .. o_{k-1} of the meta word).  Its end pe is
+// x1 for the last piece; otherwise the point where axis o_k meets its plane,
+// reached along the rest of the move, with every other coordinate clamped
+// into the piece's cell (against rounding).  Every later breakpoint of a
+// move is computed this way from the one before, on the tile path and on
+// the HBM path alike, so consecutive pieces share their breakpoints exactly
+// and the last piece ends exactly at the particle's new position.  Returns
+// the piece's start in its cell (sv) and displacement (dd).
 template <typename R>
-__device__ inline void chain_point(const R ps[3], const R x1[3], int meta, int k, R pe[3])
+__device__ inline void chain_piece(const R ps[3], const R x1[3], int meta, int k, R pe[3], int offc[3], R sv[3],
+                                   R dd[3])
 {
-    const int ax = (meta >> (4 + 2 * k)) & 3;
+    const int nb = (meta >> 2) & 3;
     int crossed = 0;
     if (k > 0) crossed |= 1 << ((meta >> 4) & 3);
     if (k > 1) crossed |= 1 << ((meta >> 6) & 3);
-    const R Dp[3] = {x1[0] - ps[0], x1[1] - ps[1], x1[2] - ps[2]};
-    const R plane = ((meta >> (10 + 2 * ax)) & 3) == 2 ? R(1) : R(0);
-    // the parameter of the crossing along the rest of the move; a rest that
-    // no longer moves along the axis (0 * inf) gives 0
-    R l = (plane - sel3(ax, ps[0], ps[1], ps[2])) * fast_rcp(sel3(ax, Dp[0], Dp[1], Dp[2]));
-    l = fmin(fmax(l, R(0)), R(1));
+    if (k > 2) crossed |= 1 << ((meta >> 8) & 3);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int da = ((meta >> (10 + 2 * a)) & 3) - 1;
-        const bool far = (crossed >> a) & 1;
-        const R v = fma(l, Dp[a], ps[a]);
-        const R pl = da > 0 ? R(1) : R(0);
-        // branch-free: keep above the plane when the
-        // axis moves up and is crossed, or moves down and is not crossed yet
-        const bool above = (da > 0) == far;
-        const R c = above ? fmax(v, pl) : fmin(v, pl);
-        pe[a] = a == ax ? plane : (da != 0 ? c : v);
+    for (int a = 0; a < 3; ++a) offc[a] = (crossed >> a) & 1 ? ((meta >> (10 + 2 * a)) & 3) - 1 : 0;
+    if (k < nb) {
+        const int ax = (meta >> (4 + 2 * k)) & 3;
+        const R Dp[3] = {x1[0] - ps[0], x1[1] - ps[1], x1[2] - ps[2]};
+        const R plane = ((meta >> (10 + 2 * ax)) & 3) == 2 ? R(1) : R(0);
+        // the parameter of the crossing along the rest of the move; a rest
+        // that no longer moves along the axis (0 * inf) gives 0
+        R l = (plane - sel3(ax, ps[0], ps[1], ps[2])) * fast_rcp(sel3(ax, Dp[0], Dp[1], Dp[2]));
+        l = fmin(fmax(l, R(0)), R(1));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const R lo = R(offc[a]);
+            const R v = fmin(fmax(fma(l, Dp[a], ps[a]), lo), lo + R(1));
+            pe[a] = a == ax ? plane : v;
+        }
+    } else {
+        pe[0] = x1[0]; pe[1] = x1[1]; pe[2] = x1[2];
     }
-}
-
-// Cell of a piece from its start ps to its end pe (home-cell frame): the
-// piece's cell offset, its start in that cell and its displacement.
-template <typename R>
-__device__ inline void piece_frame(const R ps[3], const R pe[3], int offc[3], R sv[3], R dd[3])
-{
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        offc[a] = (int)floor(R(0.5) * (ps[a] + pe[a]));
         sv[a] = ps[a] - R(offc[a]);
         dd[a] = pe[a] - ps[a];
     }
 }
 
 // The pieces k, k+1, ..., nb of a queued move, from breakpoint ps to the
-// move's end x1 (see chain_point), as the queue deposits them.
+// move's end x1 (see chain_piece), as the queue deposits them.
 // add(a, ox, oy, oz, q): rounded flux q of component a at node (cell + o).
 template <typename R, typename Add>
 __device__ inline void deposit_chain(const R ps0[3], const R x1[3], int meta, int k, R scale, Add &&add)
@@ -618,12 +619,9 @@ __device__ inline void deposit_chain(const R ps0[3], const R x1[3], int meta, in
     const int nb = (meta >> 2) & 3;
     R ps[3] = {ps0[0], ps0[1], ps0[2]};
     for (; k <= nb; ++k) {
-        R pe[3];
-        if (k < nb) chain_point(ps, x1, meta, k, pe);
-        else { pe[0] = x1[0]; pe[1] = x1[1]; pe[2] = x1[2]; }
+        R pe[3], sv[3], dd[3];
         int offc[3];
-        R sv[3], dd[3];
-        piece_frame(ps, pe, offc, sv, dd);
+        chain_piece(ps, x1, meta, k, pe, offc, sv, dd);
         piece_fluxes(sv, dd, scale, [&](int a, int f, auto q) {
             const int b1 = a == 2 ? 0 : a + 1, b2 = a == 0 ? 2 : a - 1;
             int o[3] = {offc[0], offc[1], offc[2]};
@@ -659,7 +657,7 @@ __device__ inline int move_order(const R d[3], const R D[3], int k, R x1[3], int
 // move is cut at each node plane it crosses, in order of the crossing
 // parameter, and each piece deposits its fluxes (eq. current_dep, App. A.3.4)
 // in its own cell.  The first breakpoint comes from d and the crossing
-// parameter, the later ones from chain_point, the fluxes from piece_fluxes:
+// parameter, the later ones from chain_piece, the fluxes from piece_fluxes:
 // exactly as the tile path computes them (its first piece at once, the
 // others from the queue), so a move deposits the same integers whichever
 // path it takes.  add(a, ox, oy, oz, q): rounded flux q of component a at
@@ -908,6 +906,9 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     // per neighbour direction
     __shared__ int sh_front[kMaxSpecies], sh_back[kMaxSpecies];
     __shared__ int sh_bin[kMaxSpecies][27], sh_base[kMaxSpecies][27];
+    // hand-over targets per (species, direction): first slot of the claimed
+    // part of the target tile's segment, and the segment's end
+    __shared__ int sh_tseg[kMaxSpecies][27], sh_tend[kMaxSpecies][27];
     if (tid < kMaxSpecies) {
         sh_front[tid] = 0;
         sh_back[tid] = 0;
@@ -1080,10 +1081,9 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         bool more = false;
         R pe[3] = {x1[0], x1[1], x1[2]};
         if (lane < nq) {
-            if (k < nb) chain_point(ps, x1, meta, k, pe);
             int offc[3];
             R sv[3], dd[3];
-            piece_frame(ps, pe, offc, sv, dd);
+            chain_piece(ps, x1, meta, k, pe, offc, sv, dd);
             const int cb = (w & 0x7fffffff) + offc[0] + __mul24(JX, offc[1]) + __mul24(JXY, offc[2]);
             const R sc = w < 0 ? -qscale_bits<R>() : qscale_bits<R>();
             deposit_piece<R>(jl, cb, joff, sv, dd, sc);
@@ -1134,10 +1134,9 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                 gather_global<R, F4>(B, ix, iy, iz, d, hdt, E, Bf);
             } else {
                 const R *cf = coef + __umul24(kCoef, lx | (ly << tsx) | (lz << tsxy));
-                const R pxy = d[0] * d[1], pyz = d[1] * d[2], pzx = d[2] * d[0], pxyz = pxy * d[2];
                 R F[6];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) F[c] = trilinear_eval(cf + 8 * c, d, pxy, pyz, pzx, pxyz);
+                for (int c = 0; c < 6; ++c) F[c] = trilinear_eval(cf + 8 * c, d);
                 E[0] = F[0]; E[1] = F[1]; E[2] = F[2];
                 Bf[0] = F[3]; Bf[1] = F[4]; Bf[2] = F[5];
             }
@@ -1287,6 +1286,20 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             }
         }
     }
+    // 7a. every wave is past its particle loops, so the leaver counts per
+    //     (species, direction) are final: claim their slots in the adjacent
+    //     tiles' B ranges now, one global atomic each; the replies come back
+    //     while the queues drain and the current is flushed
+    __syncthreads();
+    const int dst = C.cur ^ 1;
+    int claim = 0, ctile = 0;
+    const bool claimer = tid < C.nsp * 27;
+    const int cs = claimer ? tid / 27 : 0, ck = claimer ? tid - 27 * cs : 0;
+    const int ccnt = claimer ? sh_bin[cs][ck] : 0;
+    if (ccnt > 0) {
+        ctile = neighbor_tile(B, g, ck);
+        claim = atomicAdd(&B.sp[cs].nb[dst][ctile], ccnt);
+    }
     while (qcount > 0) drain();
     __syncthreads();
 
@@ -1303,14 +1316,16 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         }
     }
 
-    // 7. hand the staged leavers over to the adjacent tiles: one global atomic
-    //    per (species, direction) claims their slots in that tile's B range
-    const int dst = C.cur ^ 1;
-    if (tid < C.nsp * 27) {
-        const int s = tid / 27, k = tid - 27 * s;
-        const int cntk = sh_bin[s][k];
-        if (cntk > 0) sh_base[s][k] = atomicAdd(&B.sp[s].nb[dst][neighbor_tile(B, g, k)], cntk);
-        sh_bin[s][k] = 0;                         // now the rank counter
+    // 7b. hand the staged leavers over: the claimed positions and the target
+    //     segments go to LDS, so that the copies below read no layout from HBM
+    if (claimer) {
+        if (ccnt > 0) {
+            const SpeciesDev<R> &S = B.sp[cs];
+            sh_base[cs][ck] = S.bs[dst][ctile] + claim;      // position in the target's segment
+            sh_tseg[cs][ck] = S.seg_start[dst][ctile];
+            sh_tend[cs][ck] = S.seg_cap[dst][ctile];
+        }
+        sh_bin[cs][ck] = 0;                                   // now the rank counter
     }
     if (tid < C.nsp) B.sp[tid].na[dst][T] = sh_front[tid];
     __syncthreads();
@@ -1327,9 +1342,19 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             const int32_t id = Q.id ? slot_ref(Q.id, from) : 0;
             const int c3[3] = {cell_x(cell), cell_y(cell), cell_z(cell)};
             const int k = move_bin(g, rim, c3);         // the same bin as at staging
-            const int tn = neighbor_tile(B, g, k);      // the tile whose range was claimed
-            const int rank = atomicAdd(&sh_bin[s][k], 1);
-            const int at = b_range_slot(B, S, dst, tn, S.bs[dst][tn] + sh_base[s][k] + rank, C.flags);
+            const int pos = sh_base[s][k] + atomicAdd(&sh_bin[s][k], 1);
+            int at;
+            if (pos < sh_tend[s][k]) {
+                at = sh_tseg[s][k] + pos;
+            } else {                                    // the target segment is full: overflow region
+                const int o = atomicAdd(&S.nb[dst][B.ntiles], 1);
+                if (o >= S.ovf_cap) {
+                    atomicOr(C.flags, PIC_FLAG_LOST);
+                    at = -1;
+                } else {
+                    at = S.seg_start[dst][B.ntiles] + o;
+                }
+            }
             if (at >= 0) write_particle(Q, at, cell, d, u, id);
         }
     }
@@ -1787,14 +1812,14 @@ __global__ void __launch_bounds__(kBlock) diag_particles_kernel(const BoxDev<R> 
             if (in_tile) {
                 // the cell's trilinear interpolant, as the push evaluates it
                 nb = (ix - g.o[0]) + g.NX * ((iy - g.o[1]) + g.NY * (iz - g.o[2]));
-                const R pxy = d[0] * d[1], pyz = d[1] * d[2], pzx = d[2] * d[0], pxyz = pxy * d[2];
+
                 for (int c = 0; c < 3; ++c) {
                     const R *F = sE + c * g.NN + nb;
                     const int NX = g.NX, NXY = g.NX * g.NY;
                     const R f[8] = {F[0], F[1], F[NX], F[1 + NX], F[NXY], F[1 + NXY], F[NX + NXY], F[1 + NX + NXY]};
                     R cf[8];
                     trilinear_coef(f, cf);
-                    E[c] = trilinear_eval(cf, d, pxy, pyz, pzx, pxyz);
+                    E[c] = trilinear_eval(cf, d);
                 }
             } else {
                 R Bf[3];

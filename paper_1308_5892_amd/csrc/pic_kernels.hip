@@ -909,6 +909,10 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     // hand-over targets per (species, direction): first slot of the claimed
     // part of the target tile's segment, and the segment's end
     __shared__ int sh_tseg[kMaxSpecies][27], sh_tend[kMaxSpecies][27];
+    // hand-over sources per species: the arrays of copy cur^1, and the slot
+    // of leaver q of the block's combined leaver range is q + sh_loff[s]
+    __shared__ PBuf<R> sh_q[kMaxSpecies];
+    __shared__ int sh_loff[kMaxSpecies], sh_lend[kMaxSpecies];
     if (tid < kMaxSpecies) {
         sh_front[tid] = 0;
         sh_back[tid] = 0;
@@ -1296,9 +1300,15 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     const bool claimer = tid < C.nsp * 27;
     const int cs = claimer ? tid / 27 : 0, ck = claimer ? tid - 27 * cs : 0;
     const int ccnt = claimer ? sh_bin[cs][ck] : 0;
+    int tbs = 0, tseg = 0, tcap = 0;
     if (ccnt > 0) {
         ctile = neighbor_tile(B, g, ck);
         claim = atomicAdd(&B.sp[cs].nb[dst][ctile], ccnt);
+        // the target's layout, read while the queues drain
+        const SpeciesDev<R> &S = B.sp[cs];
+        tbs = S.bs[dst][ctile];
+        tseg = S.seg_start[dst][ctile];
+        tcap = S.seg_cap[dst][ctile];
     }
     while (qcount > 0) drain();
     __syncthreads();
@@ -1320,33 +1330,64 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     //     segments go to LDS, so that the copies below read no layout from HBM
     if (claimer) {
         if (ccnt > 0) {
-            const SpeciesDev<R> &S = B.sp[cs];
-            sh_base[cs][ck] = S.bs[dst][ctile] + claim;      // position in the target's segment
-            sh_tseg[cs][ck] = S.seg_start[dst][ctile];
-            sh_tend[cs][ck] = S.seg_cap[dst][ctile];
+            sh_base[cs][ck] = tbs + claim;                    // position in the target's segment
+            sh_tseg[cs][ck] = tseg;
+            sh_tend[cs][ck] = tcap;
         }
         sh_bin[cs][ck] = 0;                                   // now the rank counter
     }
-    if (tid < C.nsp) B.sp[tid].na[dst][T] = sh_front[tid];
+    if (tid < C.nsp) {
+        const SpeciesDev<R> &S = B.sp[tid];
+        S.na[dst][T] = sh_front[tid];
+        // staged leavers of species tid: slots [first, first + nl) of copy cur^1
+        const int nl = sh_back[tid];
+        int before = 0;                                       // leavers of the species before it
+        for (int s = 0; s < tid; ++s) before += sh_back[s];
+        sh_q[tid] = S.buf[dst];
+        sh_loff[tid] = S.seg_start[dst][T] + tile_ranges(S, C.cur, T).n - nl - before;
+        sh_lend[tid] = before + nl;
+    }
     __syncthreads();
-    for (int s = 0; s < C.nsp; ++s) {
-        const SpeciesDev<R> &S = B.sp[s];
-        const PBuf<R> &Q = S.buf[dst];
-        const int nl = sh_back[s];
-        const int first = S.seg_start[dst][T] + tile_ranges(S, C.cur, T).n - nl;   // staged leavers [first, first + nl)
-        for (int q = tid; q < nl; q += kBlock) {
-            const int from = first + q;
-            const int32_t cell = slot_ref(Q.cell, from);
-            const R d[3] = {slot_ref(Q.d[0], from), slot_ref(Q.d[1], from), slot_ref(Q.d[2], from)};
-            const R u[3] = {slot_ref(Q.u[0], from), slot_ref(Q.u[1], from), slot_ref(Q.u[2], from)};
-            const int32_t id = Q.id ? slot_ref(Q.id, from) : 0;
-            const int c3[3] = {cell_x(cell), cell_y(cell), cell_z(cell)};
+    // 7c. the leavers of all species form one range [0, ntot); a thread loads
+    //     up to kHand of them before it stores any, so that their HBM round
+    //     trips overlap instead of following each other
+    constexpr int kHand = 4;
+    const int ntot = C.nsp > 0 ? sh_lend[C.nsp - 1] : 0;
+    for (int q0 = tid; q0 < ntot; q0 += kHand * kBlock) {
+        int sp[kHand], cell[kHand], id[kHand];
+        R d[kHand][3], u[kHand][3];
+#pragma unroll
+        for (int h = 0; h < kHand; ++h) {
+            const int q = q0 + h * kBlock;
+            sp[h] = -1;
+            if (q < ntot) {
+                int s = 0;
+#pragma unroll
+                for (int r = 0; r + 1 < kMaxSpecies; ++r) s += (r + 1 < C.nsp && q >= sh_lend[r]) ? 1 : 0;
+                const PBuf<R> &Q = sh_q[s];
+                const int from = q + sh_loff[s];
+                cell[h] = slot_ref(Q.cell, from);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    d[h][a] = slot_ref(Q.d[a], from);
+                    u[h][a] = slot_ref(Q.u[a], from);
+                }
+                id[h] = Q.id ? slot_ref(Q.id, from) : 0;
+                sp[h] = s;
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < kHand; ++h) {
+            const int s = sp[h];
+            if (s < 0) continue;
+            const int c3[3] = {cell_x(cell[h]), cell_y(cell[h]), cell_z(cell[h])};
             const int k = move_bin(g, rim, c3);         // the same bin as at staging
             const int pos = sh_base[s][k] + atomicAdd(&sh_bin[s][k], 1);
             int at;
             if (pos < sh_tend[s][k]) {
                 at = sh_tseg[s][k] + pos;
             } else {                                    // the target segment is full: overflow region
+                const SpeciesDev<R> &S = B.sp[s];
                 const int o = atomicAdd(&S.nb[dst][B.ntiles], 1);
                 if (o >= S.ovf_cap) {
                     atomicOr(C.flags, PIC_FLAG_LOST);
@@ -1355,7 +1396,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                     at = S.seg_start[dst][B.ntiles] + o;
                 }
             }
-            if (at >= 0) write_particle(Q, at, cell, d, u, id);
+            if (at >= 0) write_particle(sh_q[s], at, cell[h], d[h], u[h], id[h]);
         }
     }
 }

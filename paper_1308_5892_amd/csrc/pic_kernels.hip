@@ -1169,9 +1169,9 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             }
 
             // new cell and offset, re-binning target, and the slot claims:
-            // the stayers' block of slots by one returning atomic of their
-            // lowest lane, each leaver its own; neither is waited for until
-            // the deposit below is done
+            // one returning LDS atomic for the stayers' block of slots and one
+            // for the leavers' staging slots, each by the lowest lane of its
+            // group, plus a per-direction count for each leaver
             // (the periodic wrap only where a lane may cross the box edge: in
             // a tile on the edge, or when a lane came from outside its tile)
             const bool anyout = __ballot(valid && !inside) != 0;

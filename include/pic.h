@@ -39,7 +39,8 @@
  * between 1 and 8, and the tile's push workgroup must fit in LDS (8x8x8 does
  * not); at most PIC_MAX_SPECIES species; fewer than 2^29 particle
  * slots (capacity x headroom, plus 32 per tile and the overflow region) per
- * species per box; dt < 1/sqrt(3) (3-D Courant bound of the Yee scheme).
+ * species per box; dt < 1/sqrt(3) (3-D Courant bound of the Yee scheme;
+ * dt < 2/sqrt(14) with PIC_FARADAY4).
  */
 #ifndef PIC_H
 #define PIC_H

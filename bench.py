@@ -37,6 +37,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle pushes/s (gather+push+deposit) at 1 GPU; % HBM roofline vs FP64 form"
 HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per cell of one FP32 push launch: e and b read (24),
+# b^{t+dt/2} of the tile's cells written (12), current flushed (24)
+PUSH_CELL_BYTES = 60.0
 PMC_FILE = os.path.join(ROOT, "profiles", "push_kernel_{}_pmc.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1308_5892_amd", "csrc", "pic_kernels.hip")
 
@@ -323,8 +326,9 @@ def main():
     tm = r32["timing"]
     push_avg_s = tm["push_ms"] / max(1, tm["push_launches"]) / 1e3
     # algorithmic bytes of one push launch: particle state read + written (28 B
-    # each way), node-field read (6 x 4 B) and current flush (3 x 8 B) per cell
-    push_bytes = 56.0 * npart + 48.0 * cells
+    # each way); per cell e and b read (6 x 4 B), b^{t+dt/2} written (3 x 4 B)
+    # and the current flushed (3 x 8 B)
+    push_bytes = 56.0 * npart + PUSH_CELL_BYTES * cells
     achieved = push_bytes / push_avg_s / 1e9
     traffic = pmc_traffic(wl)
     step_bytes = 56.0 * npart + 144.0 * cells
@@ -338,10 +342,10 @@ def main():
         p64 = t64["push_ms"] / max(1, t64["push_launches"]) / 1e3
         # this build's FP64 state is 52 B (int32 cell, 3 FP64 offsets, 3 FP64
         # u), read and written; the plain FP64 form's count is 48 B (six FP64
-        # values) each way; both with 6 x 8 B fields read and 3 x 8 B current
-        # flushed per cell
-        b64 = 104.0 * npart + 72.0 * cells
-        b64_plain = 96.0 * npart + 72.0 * cells
+        # values) each way; both with 6 x 8 B fields read, 3 x 8 B of b
+        # written and 3 x 8 B current flushed per cell
+        b64 = 104.0 * npart + 96.0 * cells
+        b64_plain = 96.0 * npart + 96.0 * cells
         fp64 = {"value": v64, "unit": "pushes/s", "steps": args.fp64_steps,
                 "push_kernel_ms": p64 * 1e3, "roofline_frac": b64 / p64 / 1e9 / HBM_PEAK_GBS,
                 "roofline_frac_96B": b64_plain / p64 / 1e9 / HBM_PEAK_GBS,
@@ -365,7 +369,7 @@ def main():
             rw = time_form(sub, False, args.steps, args.warmup, sort_interval)
             tw = rw["timing"]
             pw = tw["push_ms"] / max(1, tw["push_launches"]) / 1e3
-            bw = 56.0 * rw["npart"] + 48.0 * rw["cells"]
+            bw = 56.0 * rw["npart"] + PUSH_CELL_BYTES * rw["cells"]
             workloads.append({"workload": WORKLOAD_TEXT[name], "particles": rw["npart"], "cells": rw["cells"],
                               "pushes_per_s": rw["npart"] * args.steps / rw["seconds"],
                               "ms_per_step": rw["seconds"] / args.steps * 1e3,
@@ -385,7 +389,7 @@ def main():
                 sub["boxes"] = [dict(b, tile=tuple(tune["tiles"][0])) for b in sub["boxes"]]
             rc = time_form(sub, False, max(1, args.steps // 2), args.warmup, sort_interval)
             pc = rc["timing"]["push_ms"] / max(1, rc["timing"]["push_launches"]) / 1e3
-            bc = 56.0 * rc["npart"] + 48.0 * rc["cells"]
+            bc = 56.0 * rc["npart"] + PUSH_CELL_BYTES * rc["cells"]
             classes.append({"class": label, "boxes": len(sub["boxes"]), "particles": rc["npart"],
                             "cells": rc["cells"], "mean_theta": sum(sub["thetas"]) / len(sub["thetas"]),
                             "pushes_per_s": rc["npart"] * max(1, args.steps // 2) / rc["seconds"],

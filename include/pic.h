@@ -211,7 +211,7 @@ int pic_set_harris_field(pic_ctx *ctx, const pic_harris_field *h);
  * every sort_interval steps, and also as soon as an overflow region (the
  * slow path for particles whose tile segment is full) is half full, or holds
  * more than 8192 particles:
- * after each push the b update writes the fill of the fullest one into
+ * after each push the e update writes the fill of the fullest one into
  * coherent pinned host memory (a few bytes, allocated by pic_init), and
  * pic_step reads that report two steps later, so it keeps the stream at most
  * two steps ahead of the host instead of returning at once.  Which particles take the slow path depends

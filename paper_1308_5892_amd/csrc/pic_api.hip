@@ -66,6 +66,7 @@ static void carve(Bump &A, const pic_config *cfg, std::vector<BoxHost> &bh, std:
         D.nc = H.nc;
         D.e = A.take<R>(3 * H.nc);
         D.b = A.take<R>(3 * H.nc);
+        D.bn = A.take<R>(3 * H.nc);
         D.J = A.take<JT>(3 * H.nc);
         D.rho = A.take<double>(H.nc);
         D.acc = A.take<double>(kAccLen);
@@ -174,7 +175,9 @@ static int validate(const pic_config *cfg, std::vector<BoxHost> &bh, std::string
 }
 
 struct Layout {
-    void *boxes = nullptr;
+    // the box descriptors twice: [1] has b and bn swapped.  The push reads b
+    // and writes bn, so each step flips which array the kernels are given
+    void *boxes[2] = {nullptr, nullptr};
     Item *items_push = nullptr, *items_box = nullptr;
     CellBlock *cblocks = nullptr;
     StageItem *sitems = nullptr;
@@ -189,7 +192,8 @@ static void make_layout(const pic_config *cfg, std::vector<BoxHost> &bh, char *b
                         std::vector<BoxDev<R>> &bd)
 {
     Bump A{base};
-    L.boxes = A.take<BoxDev<R>>(cfg->n_boxes);
+    L.boxes[0] = A.take<BoxDev<R>>(cfg->n_boxes);
+    L.boxes[1] = A.take<BoxDev<R>>(cfg->n_boxes);
     L.n_items = 0;
     L.n_cblocks = 0;
     L.max_sitems = 0;
@@ -215,7 +219,7 @@ static void make_layout(const pic_config *cfg, std::vector<BoxHost> &bh, char *b
 
 using namespace pic;
 
-// Overflow watch: after every push the last block of the b update writes the
+// Overflow watch: after every push the last block of the e update writes the
 // fill of the fullest overflow region (thousandths of its capacity) straight
 // into a slot of coherent pinned host memory; pic_step reads it kWatchLag steps later
 // (waiting for that step only, so the stream stays kWatchLag steps ahead) and
@@ -242,6 +246,7 @@ struct pic_ctx {
     std::vector<Item> push_perm;            // the push order uploaded last (host copy, kept for the copy)
     int n_push = 0;                         // blocks of a push launch
     int cur = 0;
+    int bpar = 0;                           // which descriptor array holds the current b (Layout::boxes)
     int64_t step = 0;
     size_t lds_bytes = 0;
     bool fixed444 = false;             // every tile 4x4x4: the fixed-shape push kernel
@@ -269,6 +274,20 @@ struct pic_ctx {
         if (watch_host) hipHostFree(watch_host);
     }
 };
+
+// the device box descriptors in which b is the current b (b^{t-dt/2})
+template <typename R>
+static const BoxDev<R> *dev_boxes(const pic_ctx *ctx)
+{
+    return reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes[ctx->bpar]);
+}
+
+// the current b of box descriptor D (host side)
+template <typename R>
+static R *cur_b(const pic_ctx *ctx, const BoxDev<R> &D)
+{
+    return ctx->bpar ? D.bn : D.b;
+}
 
 static hipEvent_t take_event(pic_ctx *ctx)
 {
@@ -411,7 +430,7 @@ static int merge_t(pic_ctx *ctx, bool force)
                               ctx->stream));
     }
     StepConst<R> C = step_const<R>(ctx);
-    HIPCHK(launch_repack<R>(reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes), ctx->cfg.n_boxes, ctx->L.items_box,
+    HIPCHK(launch_repack<R>(dev_boxes<R>(ctx), ctx->cfg.n_boxes, ctx->L.items_box,
                             ctx->L.n_items, ctx->L.sitems, (int)si.size(), C, ctx->stream));
     ctx->cur ^= 1;
     for (int b = 0; b < ctx->cfg.n_boxes; ++b)
@@ -440,7 +459,13 @@ static int init_t(pic_ctx *ctx)
     std::vector<BoxDev<R>> &bd = bdvec<R>(ctx);
     make_layout<R>(&ctx->cfg, ctx->bh, ctx->arena, ctx->L, bd);
     HIPCHK(hipMemsetAsync(ctx->arena, 0, ctx->L.bytes - 256, ctx->stream));
-    HIPCHK(hipMemcpyAsync(ctx->L.boxes, bd.data(), bd.size() * sizeof(BoxDev<R>), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->L.boxes[0], bd.data(), bd.size() * sizeof(BoxDev<R>), hipMemcpyHostToDevice,
+                          ctx->stream));
+    std::vector<BoxDev<R>> sw = bd;
+    for (auto &D : sw) std::swap(D.b, D.bn);
+    HIPCHK(hipMemcpyAsync(ctx->L.boxes[1], sw.data(), sw.size() * sizeof(BoxDev<R>), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));   // the host copy of the swapped array is local
     // work items: per box its tiles then its overflow sweeps (box order); the
     // push order (push_order) is balanced again whenever particles are binned
     std::vector<Item> items;
@@ -529,7 +554,7 @@ int pic_init(const pic_config *cfg, void *dev_arena, size_t bytes, void *hip_str
     ctx->binned.assign(cfg->n_boxes, std::vector<int64_t>(kMaxSpecies, 0));
     ctx->stage_half.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
     ctx->next_id.assign(cfg->n_boxes, std::vector<int32_t>(kMaxSpecies, 0));
-    // the b update writes the watch straight into these slots (coherent, so
+    // the e update writes the watch straight into these slots (coherent, so
     // the host reads it once the step's event has completed): no copy per step
     if (hipHostMalloc(reinterpret_cast<void **>(&ctx->watch_host), kWatch * sizeof(uint32_t),
                       hipHostMallocCoherent) != hipSuccess) {
@@ -610,7 +635,6 @@ int pic_sync(pic_ctx *ctx)
 template <typename R>
 static int step_t(pic_ctx *ctx, int n)
 {
-    const BoxDev<R> *boxes = reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes);
     for (int i = 0; i < n; ++i) {
         // early repack when the overflow watch of kWatchLag steps ago says so
         const int64_t look = ctx->step - kWatchLag;
@@ -627,15 +651,19 @@ static int step_t(pic_ctx *ctx, int n)
         }
         StepConst<R> C = step_const<R>(ctx);
         mark(ctx, 0, true);
-        HIPCHK(launch_push<R>(boxes, ctx->L.items_push, ctx->n_push, ctx->lds_bytes, C, ctx->fixed444 ? 1 : 0,
-                              ctx->walls ? 1 : 0, (ctx->cfg.flags & PIC_FARADAY4) ? 1 : 0, ctx->stream));
+        HIPCHK(launch_push<R>(dev_boxes<R>(ctx), ctx->L.items_push, ctx->n_push, ctx->lds_bytes, C,
+                              ctx->fixed444 ? 1 : 0, ctx->walls ? 1 : 0, (ctx->cfg.flags & PIC_FARADAY4) ? 1 : 0,
+                              ctx->stream));
         mark(ctx, 0, false);
+        // the push wrote b^{t+dt/2} into the other b buffer: it is the current one now
+        ctx->bpar ^= 1;
         mark(ctx, 1, true);
-        // the b update's last block also takes the overflow watch of the copy
+        // the e update's last block also takes the overflow watch of the copy
         // just written, into the host slot of the step about to complete
         const int w = (int)((ctx->step + 1) % kWatch);
-        HIPCHK(launch_fields<R>(boxes, ctx->L.cblocks, ctx->L.n_cblocks, (R)ctx->cfg.dt, ctx->cfg.n_species, C.filter,
-                                ctx->cur, ctx->cfg.n_boxes, ctx->watch_dev + w, ctx->stream));
+        HIPCHK(launch_fields<R>(dev_boxes<R>(ctx), ctx->L.cblocks, ctx->L.n_cblocks, (R)ctx->cfg.dt,
+                                ctx->cfg.n_species, C.filter, ctx->cur, ctx->cfg.n_boxes, ctx->watch_dev + w,
+                                ctx->stream));
         mark(ctx, 1, false);
         ctx->cur ^= 1;
         ctx->step += 1;
@@ -666,7 +694,7 @@ int pic_step(pic_ctx *ctx, int n)
 template <typename R>
 static int diag_t(pic_ctx *ctx, int box, pic_diag_out *o, int64_t *hist, const DiagBuf &buf)
 {
-    const BoxDev<R> *boxes = reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes);
+    const BoxDev<R> *boxes = dev_boxes<R>(ctx);
     const BoxDev<R> &D = bdvec<R>(ctx)[box];
     const int nsp = ctx->cfg.n_species;
     const int hist_len = std::max(1, ctx->cfg.hist_bins) * kMaxSpecies;
@@ -771,7 +799,7 @@ template <typename R>
 static int spectrum_t(pic_ctx *ctx, int box, int field, int comp, int normal, double *ps)
 {
     const BoxDev<R> &D = bdvec<R>(ctx)[box];
-    const BoxDev<R> *boxes = reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes);
+    const BoxDev<R> *boxes = dev_boxes<R>(ctx);
     const int a1 = normal == 0 ? 1 : 0, a2 = normal == 2 ? 1 : 2;
     const size_t nps = (size_t)D.n[a1] * D.n[a2];
     // scratch: the box's current (cleared between steps) and its diagnostic charge array
@@ -937,7 +965,7 @@ static int get_fields_t(pic_ctx *ctx, int box, double *e, double *b, double *j)
         for (size_t q = 0; q < n3; ++q) e[q] = (double)tmp[q];
     }
     if (b) {
-        HIPCHK(hipMemcpyAsync(tmp.data(), D.b, n3 * sizeof(R), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipMemcpyAsync(tmp.data(), cur_b(ctx, D), n3 * sizeof(R), hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
         for (size_t q = 0; q < n3; ++q) b[q] = (double)tmp[q];
     }
@@ -982,7 +1010,7 @@ static int set_fields_t(pic_ctx *ctx, int box, const double *e, const double *b)
     if (b) {
         for (size_t q = 0; q < n3; ++q)
             tmp[q] = ((int)(q / D.nc) == D.wall && on_wall(q % D.nc)) ? R(0) : (R)b[q];
-        HIPCHK(hipMemcpyAsync(D.b, tmp.data(), n3 * sizeof(R), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(cur_b(ctx, D), tmp.data(), n3 * sizeof(R), hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }
     return PIC_OK;
@@ -1001,7 +1029,7 @@ static int load_t(pic_ctx *ctx, const pic_load_desc *d)
 {
     const int box = d->box;
     const BoxHost &H = ctx->bh[box];
-    const BoxDev<R> *boxes = reinterpret_cast<const BoxDev<R> *>(ctx->L.boxes);
+    const BoxDev<R> *boxes = dev_boxes<R>(ctx);
     int64_t npairs;
     if (d->profile == PIC_PROFILE_UNIFORM) {
         npairs = std::llround(d->ppc * (double)H.nc);
@@ -1102,11 +1130,11 @@ int pic_set_harris_field(pic_ctx *ctx, const pic_harris_field *h)
     }
     const int c0 = ctx->box_cblock_off[h->box], c1 = ctx->box_cblock_off[h->box + 1];
     if (ctx->fp64) {
-        const BoxDev<double> *boxes = reinterpret_cast<const BoxDev<double> *>(ctx->L.boxes);
+        const BoxDev<double> *boxes = dev_boxes<double>(ctx);
         HIPCHK(launch_harris_field<double>(boxes, ctx->bh[h->box].nc, *h, ctx->stream));
         HIPCHK(launch_advance_b<double>(boxes, ctx->L.cblocks + c0, c1 - c0, -0.5 * ctx->cfg.dt, ctx->stream));
     } else {
-        const BoxDev<float> *boxes = reinterpret_cast<const BoxDev<float> *>(ctx->L.boxes);
+        const BoxDev<float> *boxes = dev_boxes<float>(ctx);
         HIPCHK(launch_harris_field<float>(boxes, ctx->bh[h->box].nc, *h, ctx->stream));
         HIPCHK(launch_advance_b<float>(boxes, ctx->L.cblocks + c0, c1 - c0, (float)(-0.5 * ctx->cfg.dt), ctx->stream));
     }

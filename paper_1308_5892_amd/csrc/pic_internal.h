@@ -88,6 +88,7 @@ struct BoxDev {
     int64_t nc;
     PIC_GLOBAL R *e;               // 3 * nc, e^t
     PIC_GLOBAL R *b;               // 3 * nc, b^{t-dt/2}
+    PIC_GLOBAL R *bn;              // 3 * nc, the other b buffer: the push writes b^{t+dt/2} there
     PIC_GLOBAL typename JType<R>::T *J;   // 3 * nc, current of the step in flight
     PIC_GLOBAL double *rho;        // nc, diagnostic charge density
     PIC_GLOBAL double *acc;        // diagnostic accumulators (kAccLen doubles)

@@ -955,17 +955,48 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     }
     __syncthreads();
 
-    // 2. b^t = b^{t-dt/2} - (dt/2) curl e^t (App. A.3.1 item 1), in place
+    // 2. b^t = b^{t-dt/2} - (dt/2) curl e^t (App. A.3.1 item 1), in place;
+    //    and for the tile's own cells the full step b^{t+dt/2} = b^{t-dt/2} -
+    //    dt curl e^t (App. A.3.1 items 1 and 4 together), written to the other
+    //    b buffer, so that no separate b update is launched: every cell
+    //    belongs to one tile, and no block reads that buffer in this launch
     const R hdt = R(0.5) * C.dt;
+    // raw-b point (i, j, k) is a cell of this tile
+    auto own = [&](int i, int j, int k) {
+        return (unsigned)(i - 1) < (unsigned)g.ext[0] && (unsigned)(j - 1) < (unsigned)g.ext[1] &&
+               (unsigned)(k - 1) < (unsigned)g.ext[2];
+    };
+    // the new b of own raw-b point (i, j, k), the normal component zero on a
+    // conducting wall (App. A.4)
+    auto put_b = [&](int i, int j, int k, const R bnew[3]) {
+        const int gi = g.o[0] - 1 + i, gj = g.o[1] - 1 + j, gk = g.o[2] - 1 + k;
+        const int64_t gp = gi + n0 * gj + n01 * gk;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const bool wall0 = WALLS && B.wall == c && (c == 0 ? gi : (c == 1 ? gj : gk)) == 0;
+            B.bn[c * B.nc + gp] = wall0 ? R(0) : bnew[c];
+        }
+    };
     if (F4) {
         // the fourth-order curl reaches two cells out, past the staged halo:
         // b^t from HBM, exactly as the HBM path forms it
         for (int q = tid; q < g.BN; q += kBlock) {
             const int jk = div_small(q, mBX), i = q - jk * BX;
             const int k = div_small(jk, mBY), j = jk - k * g.BY;
+            const int gi = g.o[0] - 1 + i, gj = g.o[1] - 1 + j, gk = g.o[2] - 1 + k;
+            if (own(i, j, k)) {
+                R bnew[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                rb[c * g.BN + q] = bt_global<R, 1>(B, c, g.o[0] - 1 + i, g.o[1] - 1 + j, g.o[2] - 1 + k, hdt);
+                for (int c = 0; c < 3; ++c) {
+                    const R cu = curl4_e(B, c, gi, gj, gk);
+                    bnew[c] = rb[c * g.BN + q] - C.dt * cu;
+                    rb[c * g.BN + q] = rb[c * g.BN + q] - hdt * cu;
+                }
+                put_b(i, j, k, bnew);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rb[c * g.BN + q] = bt_global<R, 1>(B, c, gi, gj, gk, hdt);
+            }
         }
     } else {
         const R *ex = re, *ey = re + g.JN, *ez = re + 2 * g.JN;
@@ -973,9 +1004,17 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
             const int jk = div_small(q, mBX), i = q - jk * BX;
             const int k = div_small(jk, mBY), j = jk - k * g.BY;
             const int p = i + JX * j + JXY * k;
-            rb[q] -= hdt * ((ez[p + JX] - ez[p]) - (ey[p + JXY] - ey[p]));
-            rb[g.BN + q] -= hdt * ((ex[p + JXY] - ex[p]) - (ez[p + 1] - ez[p]));
-            rb[2 * g.BN + q] -= hdt * ((ey[p + 1] - ey[p]) - (ex[p + JX] - ex[p]));
+            const R cu[3] = {(ez[p + JX] - ez[p]) - (ey[p + JXY] - ey[p]),
+                             (ex[p + JXY] - ex[p]) - (ez[p + 1] - ez[p]),
+                             (ey[p + 1] - ey[p]) - (ex[p + JX] - ex[p])};
+            const R bo[3] = {rb[q], rb[g.BN + q], rb[2 * g.BN + q]};
+            rb[q] = bo[0] - hdt * cu[0];
+            rb[g.BN + q] = bo[1] - hdt * cu[1];
+            rb[2 * g.BN + q] = bo[2] - hdt * cu[2];
+            if (own(i, j, k)) {
+                const R bnew[3] = {bo[0] - C.dt * cu[0], bo[1] - C.dt * cu[1], bo[2] - C.dt * cu[2]};
+                put_b(i, j, k, bnew);
+            }
         }
     }
     __syncthreads();
@@ -1447,24 +1486,29 @@ __device__ void overflow_watch_block(const BoxDev<R> *__restrict__ boxes, int nb
     if (threadIdx.x == 0) *out = best;
 }
 
-// b <- b - h curl e (App. A.3.2); with old >= 0 also prepares the tile
-// descriptors of copy `old` for the next push, and with watch set takes the
-// overflow watch of copy old ^ 1 in its last block.
+// Book-keeping after a push, by the first field kernel that follows it: the
+// tile descriptors of copy `old` (the one just read) for the next push, and
+// in the grid's last block the overflow watch of copy old ^ 1 (the one just
+// written); the whole last block reaches the watch's barriers.
+template <typename R>
+__device__ inline void after_push(const BoxDev<R> *__restrict__ boxes, const BoxDev<R> &B, int64_t p, int nsp,
+                                  int old, int nboxes, uint32_t *__restrict__ watch)
+{
+    if (p < B.ntiles) next_layout(B, nsp, old, (int)p);
+    if (p == 0) next_layout(B, nsp, old, B.ntiles);
+    if (watch && blockIdx.x == gridDim.x - 1) overflow_watch_block(boxes, nboxes, nsp, old ^ 1, watch);
+}
+
+// b <- b - h curl e (App. A.3.2), in place.  The steps advance b inside the
+// push (its set-up writes b^{t+dt/2} of each tile's cells); this kernel makes
+// the half step of the start (h = -dt/2).
 template <typename R>
 __global__ void __launch_bounds__(kBlock) advance_b_kernel(const BoxDev<R> *__restrict__ boxes,
-                                                           const CellBlock *__restrict__ blocks, R h, int nsp,
-                                                           int old, int nboxes, uint32_t *__restrict__ watch)
+                                                           const CellBlock *__restrict__ blocks, R h)
 {
     const CellBlock cb = blocks[blockIdx.x];
     const BoxDev<R> &B = boxes[cb.box];
     const int64_t p = (int64_t)cb.first + threadIdx.x;
-    if (old >= 0) {
-        if (p < B.ntiles) next_layout(B, nsp, old, (int)p);
-        if (p == 0) next_layout(B, nsp, old, B.ntiles);
-    }
-    // the last block also takes the overflow watch of the copy the push just
-    // wrote (saves a launch per step); the whole block reaches the barriers
-    if (watch && blockIdx.x == gridDim.x - 1) overflow_watch_block(boxes, nboxes, nsp, old ^ 1, watch);
     if (p >= B.nc) return;
     const int n0 = B.n[0], n1 = B.n[1], n2 = B.n[2];
     const int i = (int)(p % n0), j = (int)((p / n0) % n1), k = (int)(p / ((int64_t)n0 * n1));
@@ -1489,15 +1533,18 @@ __global__ void __launch_bounds__(kBlock) advance_b_kernel(const BoxDev<R> *__re
         B.b[B.wall * B.nc + p] = R(0);           // normal b on a conducting wall (App. A.4)
 }
 
-// e <- e + dt curl b + alpha0 J (App. A.3.2 and A.2, eq. max2bis); J <- 0.
+// e <- e + dt curl b + alpha0 J (App. A.3.2 and A.2, eq. max2bis); J <- 0;
+// and the book-keeping after the push (after_push).
 template <typename R>
 __global__ void __launch_bounds__(kBlock) advance_e_kernel(const BoxDev<R> *__restrict__ boxes,
-                                                           const CellBlock *__restrict__ blocks, R dt)
+                                                           const CellBlock *__restrict__ blocks, R dt, int nsp,
+                                                           int old, int nboxes, uint32_t *__restrict__ watch)
 {
     using JT = typename JType<R>::T;
     const CellBlock cb = blocks[blockIdx.x];
     const BoxDev<R> &B = boxes[cb.box];
     const int64_t p = (int64_t)cb.first + threadIdx.x;
+    after_push(boxes, B, p, nsp, old, nboxes, watch);
     if (p >= B.nc) return;
     const int n0 = B.n[0], n1 = B.n[1], n2 = B.n[2];
     const int i = (int)(p % n0), j = (int)((p / n0) % n1), k = (int)(p / ((int64_t)n0 * n1));
@@ -1554,12 +1601,15 @@ __device__ inline T smooth27(const PIC_GLOBAL T *f, const int n[3], int i, int j
 // clear_current_kernel, since every cell reads its neighbours' J here.
 template <typename R>
 __global__ void __launch_bounds__(kBlock) advance_e_smoothed_kernel(const BoxDev<R> *__restrict__ boxes,
-                                                                    const CellBlock *__restrict__ blocks, R dt)
+                                                                    const CellBlock *__restrict__ blocks, R dt,
+                                                                    int nsp, int old, int nboxes,
+                                                                    uint32_t *__restrict__ watch)
 {
     using JT = typename JType<R>::T;
     const CellBlock cb = blocks[blockIdx.x];
     const BoxDev<R> &B = boxes[cb.box];
     const int64_t p = (int64_t)cb.first + threadIdx.x;
+    after_push(boxes, B, p, nsp, old, nboxes, watch);
     if (p >= B.nc) return;
     const int n0 = B.n[0], n1 = B.n[1], n2 = B.n[2];
     const int i = (int)(p % n0), j = (int)((p / n0) % n1), k = (int)(p / ((int64_t)n0 * n1));
@@ -1987,13 +2037,13 @@ template <typename R>
 hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R dt, int nsp, int filter,
                          int clear_copy, int nboxes, uint32_t *watch, hipStream_t st)
 {
-    hipLaunchKernelGGL(advance_b_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt, nsp, clear_copy,
-                       nboxes, watch);
     if (filter) {
-        hipLaunchKernelGGL(advance_e_smoothed_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt);
+        hipLaunchKernelGGL(advance_e_smoothed_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt, nsp,
+                           clear_copy, nboxes, watch);
         hipLaunchKernelGGL(clear_current_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks);
     } else {
-        hipLaunchKernelGGL(advance_e_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt);
+        hipLaunchKernelGGL(advance_e_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, dt, nsp,
+                           clear_copy, nboxes, watch);
     }
     return hipGetLastError();
 }
@@ -2001,8 +2051,7 @@ hipError_t launch_fields(const BoxDev<R> *boxes, const CellBlock *blocks, int nb
 template <typename R>
 hipError_t launch_advance_b(const BoxDev<R> *boxes, const CellBlock *blocks, int nblocks, R h, hipStream_t st)
 {
-    hipLaunchKernelGGL(advance_b_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, h, 0, -1, 0,
-                       (uint32_t *)nullptr);
+    hipLaunchKernelGGL(advance_b_kernel<R>, dim3(nblocks), dim3(kBlock), 0, st, boxes, blocks, h);
     return hipGetLastError();
 }
 

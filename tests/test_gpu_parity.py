@@ -300,7 +300,7 @@ def test_overflow_region_keeps_parity(fp64):
 def test_overflow_watch_repacks_early(fp64):
     # no periodic repack: an eighth of the particles stream into tiles laid
     # out empty, the overflow region (1024 particles per species) fills past
-    # half, and the overflow watch, written by the b update into host memory,
+    # half, and the overflow watch, written by the e update into host memory,
     # has pic_step repack before the region runs out; nothing is lost and the
     # run follows the oracle
     from paper_1308_5892_amd import pic as P

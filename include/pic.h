@@ -285,7 +285,9 @@ typedef struct pic_timing {
     double  sort_ms;
 } pic_timing;
 
-/* Turn event recording in pic_step on (1) or off (0). */
+/* Event recording in pic_step: 0 off, 1 around every push, field update and
+ * repack, 2 around the push only (fewer events in the stream; each costs a
+ * few microseconds of the step).  Other values: PIC_EINVAL. */
 int pic_set_timing(pic_ctx *ctx, int enable);
 
 /* Sum the recorded intervals into *out (synchronises); reset != 0 forgets them. */

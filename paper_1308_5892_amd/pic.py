@@ -252,7 +252,8 @@ def pic_steps_done(ctx):
 
 
 def pic_set_timing(ctx, enable):
-    _check(lib().pic_set_timing(ctx, int(bool(enable))), ctx)
+    """0 off, 1 (or True) every launch kind, 2 the push only."""
+    _check(lib().pic_set_timing(ctx, int(enable)), ctx)
 
 
 def pic_get_timing(ctx, reset=True):

@@ -481,6 +481,14 @@ def test_repack_keeps_parity(fp64):
     for sp in range(2):
         _, u, _ = s.particles(0, sp)
         assert G.u_rel_err(u, st.u[st.species == sp], 1e-3).max() < (1e-11 if fp64 else U32)
+    # timing mode 2 times the push launches only; other modes are refused
+    P.pic_set_timing(s.ctx, 2)
+    s.step(4)
+    t = P.pic_get_timing(s.ctx)
+    assert t["push_launches"] == 4 and t["push_ms"] > 0.0
+    assert t["field_launches"] == 0 and t["sort_launches"] == 0
+    with pytest.raises(P.PicError):
+        P.pic_set_timing(s.ctx, 3)
     s.close()
 
 

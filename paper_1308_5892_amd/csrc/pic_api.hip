@@ -106,8 +106,8 @@ static void carve(Bump &A, const pic_config *cfg, std::vector<BoxHost> &bh, std:
 }
 
 // LDS one workgroup may allocate on gfx950 (160 KiB per CU, minus the push
-// kernel's static counters)
-constexpr size_t kMaxLds = 160 * 1024 - 2048;
+// kernel's static counters and tables)
+constexpr size_t kMaxLds = 160 * 1024 - 2176;
 
 static int validate(const pic_config *cfg, std::vector<BoxHost> &bh, std::string &err)
 {

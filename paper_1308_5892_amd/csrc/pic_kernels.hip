@@ -289,20 +289,6 @@ __device__ inline TileRanges tile_ranges(const SpeciesDev<R> &S, int c, int T)
     return r;
 }
 
-// The same for a tile index that is uniform over the wave: the values are
-// kept in scalar registers.
-template <typename R>
-__device__ inline TileRanges tile_ranges_uniform(const SpeciesDev<R> &S, int c, int T)
-{
-    const TileRanges v = tile_ranges(S, c, T);
-    TileRanges r;
-    r.start = __builtin_amdgcn_readfirstlane(v.start);
-    r.na = __builtin_amdgcn_readfirstlane(v.na);
-    r.bs = __builtin_amdgcn_readfirstlane(v.bs);
-    r.n = __builtin_amdgcn_readfirstlane(v.n);
-    return r;
-}
-
 // The overflow region of copy c as a range.
 template <typename R>
 __device__ inline TileRanges overflow_range(const BoxDev<R> &B, const SpeciesDev<R> &S, int c)
@@ -913,11 +899,23 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     // of leaver q of the block's combined leaver range is q + sh_loff[s]
     __shared__ PBuf<R> sh_q[kMaxSpecies];
     __shared__ int sh_loff[kMaxSpecies], sh_lend[kMaxSpecies];
+    // per species the tile's ranges in copy cur (start, na, bs, n) and its
+    // segment start in copy cur^1, read here, while the fields are staged,
+    // instead of at the start of each species' loop and in the hand-over
+    __shared__ int sh_rng[kMaxSpecies][5];
     if (tid < kMaxSpecies) {
         sh_front[tid] = 0;
         sh_back[tid] = 0;
     }
     if (tid < kMaxSpecies * 27) (&sh_bin[0][0])[tid] = 0;
+    if (tid < C.nsp) {
+        const TileRanges r = tile_ranges(B.sp[tid], C.cur, T);
+        sh_rng[tid][0] = r.start;
+        sh_rng[tid][1] = r.na;
+        sh_rng[tid][2] = r.bs;
+        sh_rng[tid][3] = r.n;
+        sh_rng[tid][4] = B.sp[tid].seg_start[C.cur ^ 1][T];
+    }
 
     // region indices are decoded by multiply-shift (edges of at most 11 and
     // fewer than 2^11 points: exact)
@@ -1137,13 +1135,17 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     for (int s = 0; s < C.nsp; ++s) {
         const SpeciesDev<R> &S = B.sp[s];
         const PBuf<R> &P = S.buf[C.cur];
-        const TileRanges src = tile_ranges_uniform(S, C.cur, T);
+        TileRanges src;
+        src.start = __builtin_amdgcn_readfirstlane(sh_rng[s][0]);
+        src.na = __builtin_amdgcn_readfirstlane(sh_rng[s][1]);
+        src.bs = __builtin_amdgcn_readfirstlane(sh_rng[s][2]);
+        src.n = __builtin_amdgcn_readfirstlane(sh_rng[s][3]);
         const int n = src.n;
         const R hk = R(0.5) * C.kq[s] * C.dt;
         const R scale = -C.qs[s] * qscale_bits<R>();
         const int32_t sgnbit = scale < R(0) ? (int32_t)0x80000000 : 0;
         const int dst = C.cur ^ 1;
-        const int dst_start = __builtin_amdgcn_readfirstlane(S.seg_start[dst][T]);
+        const int dst_start = __builtin_amdgcn_readfirstlane(sh_rng[s][4]);
         // the particle of the next iteration is loaded one iteration ahead, so
         // that its HBM latency is covered by the work on the current one;
         // lanes past the end load the tile's last particle again and are
@@ -1383,7 +1385,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         int before = 0;                                       // leavers of the species before it
         for (int s = 0; s < tid; ++s) before += sh_back[s];
         sh_q[tid] = S.buf[dst];
-        sh_loff[tid] = S.seg_start[dst][T] + tile_ranges(S, C.cur, T).n - nl - before;
+        sh_loff[tid] = sh_rng[tid][4] + sh_rng[tid][3] - nl - before;
         sh_lend[tid] = before + nl;
     }
     __syncthreads();

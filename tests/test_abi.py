@@ -77,9 +77,9 @@ def test_push_kernels_keep_their_register_budget(P, tmp_path):
         name = re.search(r"\.name:\s+(\S+)", block).group(1)
         if not name.startswith("_ZN3pic11push_kernel"):
             continue
-        # every push kernel's static LDS fits the 2 KiB that pic_plan keeps
+        # every push kernel's static LDS fits the 2176 B that pic_plan keeps
         # back from the 160 KiB when it sizes a tile's dynamic LDS
-        assert int(re.search(r"\.group_segment_fixed_size:\s+(\d+)", block).group(1)) <= 2048, name
+        assert int(re.search(r"\.group_segment_fixed_size:\s+(\d+)", block).group(1)) <= 2176, name
         if not name.startswith("_ZN3pic11push_kernelIf"):
             continue
         found += 1

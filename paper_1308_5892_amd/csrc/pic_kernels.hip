@@ -953,6 +953,33 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     }
     __syncthreads();
 
+    // the particle loops load each lane's next particle one iteration ahead
+    // (lanes past the end load the tile's last particle again and are masked
+    // out of every store, claim and deposit by `valid`); the first particle
+    // of species 0 is loaded here, so that its HBM latency is covered by the
+    // rest of the set-up
+    int32_t nx_cell = 0, nx_id = 0;
+    R nx_d[3] = {R(0.5), R(0.5), R(0.5)}, nx_u[3] = {R(0), R(0), R(0)};
+    auto fetch_particle = [&](const PBuf<R> &P, const TileRanges &src, int q) {
+        const int at = src.slot(min(q, src.n - 1));
+        nx_cell = slot_ref(P.cell, at);
+        nx_d[0] = slot_ref(P.d[0], at); nx_d[1] = slot_ref(P.d[1], at); nx_d[2] = slot_ref(P.d[2], at);
+        nx_u[0] = slot_ref(P.u[0], at); nx_u[1] = slot_ref(P.u[1], at); nx_u[2] = slot_ref(P.u[2], at);
+        if (P.id) nx_id = slot_ref(P.id, at);
+    };
+    auto ranges = [&](int s) {
+        TileRanges r;
+        r.start = __builtin_amdgcn_readfirstlane(sh_rng[s][0]);
+        r.na = __builtin_amdgcn_readfirstlane(sh_rng[s][1]);
+        r.bs = __builtin_amdgcn_readfirstlane(sh_rng[s][2]);
+        r.n = __builtin_amdgcn_readfirstlane(sh_rng[s][3]);
+        return r;
+    };
+    {
+        const TileRanges r0 = ranges(0);
+        if (r0.n > 0) fetch_particle(B.sp[0].buf[C.cur], r0, tid);
+    }
+
     // 2. b^t = b^{t-dt/2} - (dt/2) curl e^t (App. A.3.1 item 1), in place;
     //    and for the tile's own cells the full step b^{t+dt/2} = b^{t-dt/2} -
     //    dt curl e^t (App. A.3.1 items 1 and 4 together), written to the other
@@ -1135,31 +1162,15 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     for (int s = 0; s < C.nsp; ++s) {
         const SpeciesDev<R> &S = B.sp[s];
         const PBuf<R> &P = S.buf[C.cur];
-        TileRanges src;
-        src.start = __builtin_amdgcn_readfirstlane(sh_rng[s][0]);
-        src.na = __builtin_amdgcn_readfirstlane(sh_rng[s][1]);
-        src.bs = __builtin_amdgcn_readfirstlane(sh_rng[s][2]);
-        src.n = __builtin_amdgcn_readfirstlane(sh_rng[s][3]);
+        const TileRanges src = ranges(s);
         const int n = src.n;
         const R hk = R(0.5) * C.kq[s] * C.dt;
         const R scale = -C.qs[s] * qscale_bits<R>();
         const int32_t sgnbit = scale < R(0) ? (int32_t)0x80000000 : 0;
         const int dst = C.cur ^ 1;
         const int dst_start = __builtin_amdgcn_readfirstlane(sh_rng[s][4]);
-        // the particle of the next iteration is loaded one iteration ahead, so
-        // that its HBM latency is covered by the work on the current one;
-        // lanes past the end load the tile's last particle again and are
-        // masked out of every store, claim and deposit by `valid`
-        int32_t nx_cell = 0, nx_id = 0;
-        R nx_d[3] = {R(0.5), R(0.5), R(0.5)}, nx_u[3] = {R(0), R(0), R(0)};
-        auto fetch = [&](int q) {
-            const int at = src.slot(min(q, n - 1));
-            nx_cell = slot_ref(P.cell, at);
-            nx_d[0] = slot_ref(P.d[0], at); nx_d[1] = slot_ref(P.d[1], at); nx_d[2] = slot_ref(P.d[2], at);
-            nx_u[0] = slot_ref(P.u[0], at); nx_u[1] = slot_ref(P.u[1], at); nx_u[2] = slot_ref(P.u[2], at);
-            if (P.id) nx_id = slot_ref(P.id, at);
-        };
-        if (n > 0) fetch(tid);
+        auto fetch = [&](int q) { fetch_particle(P, src, q); };
+        if (n > 0 && s > 0) fetch(tid);                  // species 0: loaded during the set-up
         for (int pb = 0; pb < n; pb += kBlock) {
             const int p = pb + tid;
             const bool valid = p < n;

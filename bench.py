@@ -327,8 +327,10 @@ def main():
     tm = r32["timing"]
     push_avg_s = tm["push_ms"] / max(1, tm["push_launches"]) / 1e3
     # algorithmic bytes of one push launch: particle state read + written (28 B
-    # each way); per cell e and b read (6 x 4 B), b^{t+dt/2} written (3 x 4 B)
-    # and the current flushed (3 x 8 B)
+    # each way: packed cell, 3 offsets, 3 momenta; the library stores the cell
+    # of a binned particle as a one-byte tile-local code, so it moves 25 B each
+    # way); per cell e and b read (6 x 4 B), b^{t+dt/2} written (3 x 4 B) and
+    # the current flushed (3 x 8 B)
     push_bytes = 56.0 * npart + PUSH_CELL_BYTES * cells
     achieved = push_bytes / push_avg_s / 1e9
     traffic = pmc_traffic(wl)
@@ -340,11 +342,11 @@ def main():
         v64 = r64["npart"] * args.fp64_steps / r64["seconds"]
         t64 = r64["timing"]
         p64 = t64["push_ms"] / max(1, t64["push_launches"]) / 1e3
-        # this build's FP64 state is 52 B (int32 cell, 3 FP64 offsets, 3 FP64
-        # u), read and written; the plain FP64 form's count is 48 B (six FP64
-        # values) each way; both with 6 x 8 B fields read, 3 x 8 B of b
-        # written and 3 x 8 B current flushed per cell
-        b64 = 104.0 * npart + 96.0 * cells
+        # this build's FP64 state is 49 B (one-byte tile-local cell, 3 FP64
+        # offsets, 3 FP64 u), read and written; the plain FP64 form's count is
+        # 48 B (six FP64 values) each way; both with 6 x 8 B fields read,
+        # 3 x 8 B of b written and 3 x 8 B current flushed per cell
+        b64 = 98.0 * npart + 96.0 * cells
         b64_plain = 96.0 * npart + 96.0 * cells
         fp64 = {"value": v64, "unit": "pushes/s", "steps": args.fp64_steps,
                 "push_kernel_ms": p64 * 1e3, "roofline_frac": b64 / p64 / 1e9 / HBM_PEAK_GBS,

@@ -80,6 +80,7 @@ static void carve(Bump &A, const pic_config *cfg, std::vector<BoxHost> &bh, std:
             if (s >= cfg->n_species) continue;
             const size_t n = H.slots[s], ns = H.stage_cap[s];
             for (int c = 0; c < 2; ++c) {
+                S.buf[c].lc = A.take<uint8_t>(n);
                 S.buf[c].cell = A.take<int32_t>(n);
                 for (int a = 0; a < 3; ++a) S.buf[c].d[a] = A.take<R>(n);
                 for (int a = 0; a < 3; ++a) S.buf[c].u[a] = A.take<R>(n);
@@ -860,7 +861,9 @@ static int get_particles_t(pic_ctx *ctx, int box, int s, double *x, double *u, i
     std::vector<int32_t> cell(ns), pid(S.buf[ctx->cur].id ? ns : 0);
     std::vector<R> dd[3], uu[3];
     const PBuf<R> &P = S.buf[ctx->cur];
+    std::vector<uint8_t> code(ns);
     HIPCHK(hipMemcpyAsync(cell.data(), P.cell, ns * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(code.data(), P.lc, ns, hipMemcpyDeviceToHost, ctx->stream));
     for (int a = 0; a < 3; ++a) {
         dd[a].resize(ns);
         uu[a].resize(ns);
@@ -869,6 +872,20 @@ static int get_particles_t(pic_ctx *ctx, int box, int s, double *x, double *u, i
     }
     if (P.id) HIPCHK(hipMemcpyAsync(pid.data(), P.id, ns * 4, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    // a tile's ranges hold tile-local cell codes: the packed cell is the
+    // tile's origin plus the code's bits
+    const int sx = D.tshift[0], sy = D.tshift[1];
+    for (int t = 0; t < nt; ++t) {
+        const int r = t / D.ntile[0];
+        const int o[3] = {(t - r * D.ntile[0]) << sx, (r % D.ntile[1]) << sy, (r / D.ntile[1]) << D.tshift[2]};
+        auto decode = [&](int64_t k) {
+            const int c = code[k];
+            cell[k] = pack_cell(o[0] + (c & ((1 << sx) - 1)), o[1] + ((c >> sx) & ((1 << sy) - 1)), o[2] + (c >> (sx + sy)));
+        };
+        for (int k = 0; k < na[t]; ++k) decode(start[t] + k);
+        const int nbv = std::max(0, std::min(nb[t], cap[t] - bs[t]));
+        for (int k = 0; k < nbv; ++k) decode(start[t] + bs[t] + k);
+    }
     if (P.id) std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return pid[a] < pid[b]; });
     for (int64_t q = 0; q < total; ++q) {
         const int64_t k = order[q];

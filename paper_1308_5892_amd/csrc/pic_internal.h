@@ -52,9 +52,16 @@ __host__ __device__ inline int cell_x(int32_t c) { return (int)((uint32_t)c & 20
 __host__ __device__ inline int cell_y(int32_t c) { return (int)(((uint32_t)c >> 11) & 2047u); }
 __host__ __device__ inline int cell_z(int32_t c) { return (int)((uint32_t)c >> 22); }
 
+// A particle in a tile's ranges keeps its cell as a one-byte code local to
+// the tile, x | y << tx | z << (tx + ty) (tile edges 2^tx, 2^ty, 2^tz, at most
+// 256 cells; tiles start at multiples of their edges, so the code is the low
+// bits of the cell's coordinates).  The overflow region, whose particles
+// belong to any tile, and the leavers a push stages for the hand-over keep the
+// packed cell.
 template <typename R>
 struct PBuf {                      // one copy of the particle arrays
-    PIC_GLOBAL int32_t *cell;
+    PIC_GLOBAL uint8_t *lc;        // tile-local cell code (tile ranges); nullptr in the stage
+    PIC_GLOBAL int32_t *cell;      // packed cell (overflow region, staged leavers, stage)
     PIC_GLOBAL R *d[3];
     PIC_GLOBAL R *u[3];
     PIC_GLOBAL int32_t *id;        // nullptr without PIC_TRACK_IDS
@@ -139,6 +146,33 @@ __device__ inline int tile_of(const BoxDev<R> &B, int32_t c)
     const unsigned ty = (unsigned)(cell_y(c) >> B.tshift[1]), tz = (unsigned)(cell_z(c) >> B.tshift[2]);
     return (cell_x(c) >> B.tshift[0]) +
            (int)__umul24((unsigned)B.ntile[0], ty + __umul24((unsigned)B.ntile[1], tz));
+}
+
+// Tile-local code of a cell (the low bits of its coordinates) and its inverse
+// for a tile with origin o.
+template <typename R>
+__device__ inline int local_code(const BoxDev<R> &B, int32_t c)
+{
+    const int sx = B.tshift[0], sy = B.tshift[1];
+    return (cell_x(c) & ((1 << sx) - 1)) | ((cell_y(c) & ((1 << sy) - 1)) << sx) |
+           ((cell_z(c) & ((1 << B.tshift[2]) - 1)) << (sx + sy));
+}
+
+template <typename R>
+__device__ inline int32_t local_cell(const BoxDev<R> &B, const int o[3], int code)
+{
+    const int sx = B.tshift[0], sy = B.tshift[1];
+    return pack_cell(o[0] + (code & ((1 << sx) - 1)), o[1] + ((code >> sx) & ((1 << sy) - 1)), o[2] + (code >> (sx + sy)));
+}
+
+// Origin cell of tile T.
+template <typename R>
+__device__ inline void tile_origin(const BoxDev<R> &B, int T, int o[3])
+{
+    const int r = T / B.ntile[0];
+    o[0] = (T - r * B.ntile[0]) << B.tshift[0];
+    o[1] = (r % B.ntile[1]) << B.tshift[1];
+    o[2] = (r / B.ntile[1]) << B.tshift[2];
 }
 
 // cell blocks of the field kernels: (box, first cell) of kBlock cells

@@ -234,10 +234,15 @@ __device__ inline PIC_GLOBAL T &slot_ref(PIC_GLOBAL T *base, int i)
                                              (uint32_t)i * (uint32_t)sizeof(T));
 }
 
+// Store a particle at slot `at` of copy P.  wide: the slot is in the overflow
+// region or stages a leaver, and takes the packed cell; otherwise it is in
+// the ranges of the cell's tile and takes the tile-local code.
 template <typename R>
-__device__ inline void write_particle(const PBuf<R> &P, int at, int32_t cell, const R d[3], const R u[3], int32_t id)
+__device__ inline void write_particle(const PBuf<R> &P, int at, bool wide, int32_t cell, int code, const R d[3],
+                                      const R u[3], int32_t id)
 {
-    slot_ref(P.cell, at) = cell;
+    if (wide) slot_ref(P.cell, at) = cell;
+    else slot_ref(P.lc, at) = (uint8_t)code;
     slot_ref(P.d[0], at) = d[0]; slot_ref(P.d[1], at) = d[1]; slot_ref(P.d[2], at) = d[2];
     slot_ref(P.u[0], at) = u[0]; slot_ref(P.u[1], at) = u[1]; slot_ref(P.u[2], at) = u[2];
     if (P.id) slot_ref(P.id, at) = id;
@@ -269,7 +274,7 @@ __device__ inline void store_particle(const BoxDev<R> &B, const SpeciesDev<R> &S
     const int slot = claim_slot(S.nb[dst], tgt, valid);
     if (!valid) return;
     const int at = b_range_slot(B, S, dst, tgt, S.bs[dst][tgt] + slot, flags);
-    if (at >= 0) write_particle(S.buf[dst], at, cell, d, u, id);
+    if (at >= 0) write_particle(S.buf[dst], at, at >= S.slots - S.ovf_cap, cell, local_code(B, cell), d, u, id);
 }
 
 // The particles of tile T in copy c: the A range then the clamped B range.
@@ -878,6 +883,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     // LDS: per-cell trilinear coefficients | piece queues | union of {raw e,
     // raw b, node fields} (set-up) and the tile current (particle loop)
     const int tsx = FIX ? 2 : B.tshift[0], tsxy = FIX ? 4 : B.tshift[0] + B.tshift[1];
+    const int tsz = FIX ? 2 : B.tshift[2];
     const TileLds lds = FIX ? tile_lds<R>(4, 4, 4) : tile_lds<R>(1 << B.tshift[0], 1 << B.tshift[1], 1 << B.tshift[2]);
     R *coef = reinterpret_cast<R *>(smem);
     unsigned char *qmem = smem + lds.coef;
@@ -958,11 +964,11 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     // out of every store, claim and deposit by `valid`); the first particle
     // of species 0 is loaded here, so that its HBM latency is covered by the
     // rest of the set-up
-    int32_t nx_cell = 0, nx_id = 0;
+    int32_t nx_code = 0, nx_id = 0;
     R nx_d[3] = {R(0.5), R(0.5), R(0.5)}, nx_u[3] = {R(0), R(0), R(0)};
     auto fetch_particle = [&](const PBuf<R> &P, const TileRanges &src, int q) {
         const int at = src.slot(min(q, src.n - 1));
-        nx_cell = slot_ref(P.cell, at);
+        nx_code = slot_ref(P.lc, at);
         nx_d[0] = slot_ref(P.d[0], at); nx_d[1] = slot_ref(P.d[1], at); nx_d[2] = slot_ref(P.d[2], at);
         nx_u[0] = slot_ref(P.u[0], at); nx_u[1] = slot_ref(P.u[1], at); nx_u[2] = slot_ref(P.u[2], at);
         if (P.id) nx_id = slot_ref(P.id, at);
@@ -1169,19 +1175,20 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         const int32_t sgnbit = scale < R(0) ? (int32_t)0x80000000 : 0;
         const int dst = C.cur ^ 1;
         const int dst_start = __builtin_amdgcn_readfirstlane(sh_rng[s][4]);
+        const int ovf0 = S.slots - S.ovf_cap;           // first slot of the overflow region
         auto fetch = [&](int q) { fetch_particle(P, src, q); };
         if (n > 0 && s > 0) fetch(tid);                  // species 0: loaded during the set-up
         for (int pb = 0; pb < n; pb += kBlock) {
             const int p = pb + tid;
             const bool valid = p < n;
-            const int32_t cell = nx_cell, id = nx_id;
+            const int code = nx_code, id = nx_id;
             R d[3] = {nx_d[0], nx_d[1], nx_d[2]}, u[3] = {nx_u[0], nx_u[1], nx_u[2]};
             if (pb + kBlock < n) fetch(p + kBlock);
-            const int ix = cell_x(cell), iy = cell_y(cell), iz = cell_z(cell);
-            const int lx = ix - g.o[0], ly = iy - g.o[1], lz = iz - g.o[2];
-            // every particle of the segment has its cell in the tile; anything
-            // else would index the tile's LDS out of range, so it takes the
-            // HBM path instead
+            const int lx = code & ((1 << tsx) - 1), ly = (code >> tsx) & ((1 << (tsxy - tsx)) - 1), lz = code >> tsxy;
+            const int ix = g.o[0] + lx, iy = g.o[1] + ly, iz = g.o[2] + lz;
+            // a particle of the tile's ranges has its cell in the tile; a code
+            // past a partial tile's extent would index the tile's LDS out of
+            // range, so it takes the HBM path instead
             const bool inside = (unsigned)lx < (unsigned)g.ext[0] && (unsigned)ly < (unsigned)g.ext[1] &&
                                 (unsigned)lz < (unsigned)g.ext[2];
             // gather: the cell's trilinear interpolant at the in-cell offset
@@ -1239,6 +1246,8 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                 cn[a] = ci;
             }
             const int32_t ncell = pack_cell(cn[0], cn[1], cn[2]);
+            const int ncode = (cn[0] & ((1 << tsx) - 1)) | ((cn[1] & ((1 << (tsxy - tsx)) - 1)) << tsx) |
+                              ((cn[2] & ((1 << tsz) - 1)) << tsxy);
             const int tn = tile_of(B, ncell);
             // re-binning: stayers take the next slots at the front of the
             // tile's new A range, leavers into an adjacent tile are staged from
@@ -1277,7 +1286,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                 const int slot = atomicAdd(&S.nb[dst][tn], 1);
                 at = b_range_slot(B, S, dst, tn, S.bs[dst][tn] + slot, C.flags);
             }
-            if (at >= 0) write_particle(S.buf[dst], at, ncell, dn, u, id);
+            if (at >= 0) write_particle(S.buf[dst], at, lv || at >= ovf0, ncell, ncode, dn, u, id);
 
             // deposit: the first piece (in the home cell) at once, the move
             // into the wave's queue for its later pieces; the crossings in
@@ -1362,6 +1371,50 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         tseg = S.seg_start[dst][ctile];
         tcap = S.seg_cap[dst][ctile];
     }
+    if (tid < C.nsp) {
+        const SpeciesDev<R> &S = B.sp[tid];
+        S.na[dst][T] = sh_front[tid];
+        // staged leavers of species tid: slots [first, first + nl) of copy cur^1
+        const int nl = sh_back[tid];
+        int before = 0;                                       // leavers of the species before it
+        for (int s = 0; s < tid; ++s) before += sh_back[s];
+        sh_q[tid] = S.buf[dst];
+        sh_loff[tid] = sh_rng[tid][4] + sh_rng[tid][3] - nl - before;
+        sh_lend[tid] = before + nl;
+    }
+    __syncthreads();
+    // the staged leavers of all species form one range [0, ntot); a thread
+    // loads up to kHand of them before it stores any, so that their HBM round
+    // trips overlap instead of following each other.  The first batch is
+    // loaded here: its round trips overlap the claims' replies, the drains
+    // and the flush.
+    constexpr int kHand = 4;
+    const int ntot = C.nsp > 0 ? sh_lend[C.nsp - 1] : 0;
+    int hsp[kHand], hcell[kHand], hid[kHand];
+    R hd[kHand][3], hu[kHand][3];
+    auto load_leavers = [&](int q0) {
+#pragma unroll
+        for (int h = 0; h < kHand; ++h) {
+            const int q = q0 + h * kBlock;
+            hsp[h] = -1;
+            if (q < ntot) {
+                int s = 0;
+#pragma unroll
+                for (int r = 0; r + 1 < kMaxSpecies; ++r) s += (r + 1 < C.nsp && q >= sh_lend[r]) ? 1 : 0;
+                const PBuf<R> &Q = sh_q[s];
+                const int from = q + sh_loff[s];
+                hcell[h] = slot_ref(Q.cell, from);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    hd[h][a] = slot_ref(Q.d[a], from);
+                    hu[h][a] = slot_ref(Q.u[a], from);
+                }
+                hid[h] = Q.id ? slot_ref(Q.id, from) : 0;
+                hsp[h] = s;
+            }
+        }
+    };
+    load_leavers(tid);
     while (qcount > 0) drain();
     __syncthreads();
 
@@ -1388,55 +1441,21 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
         }
         sh_bin[cs][ck] = 0;                                   // now the rank counter
     }
-    if (tid < C.nsp) {
-        const SpeciesDev<R> &S = B.sp[tid];
-        S.na[dst][T] = sh_front[tid];
-        // staged leavers of species tid: slots [first, first + nl) of copy cur^1
-        const int nl = sh_back[tid];
-        int before = 0;                                       // leavers of the species before it
-        for (int s = 0; s < tid; ++s) before += sh_back[s];
-        sh_q[tid] = S.buf[dst];
-        sh_loff[tid] = sh_rng[tid][4] + sh_rng[tid][3] - nl - before;
-        sh_lend[tid] = before + nl;
-    }
     __syncthreads();
-    // 7c. the leavers of all species form one range [0, ntot); a thread loads
-    //     up to kHand of them before it stores any, so that their HBM round
-    //     trips overlap instead of following each other
-    constexpr int kHand = 4;
-    const int ntot = C.nsp > 0 ? sh_lend[C.nsp - 1] : 0;
+    // 7c. store each loaded leaver at its claimed slot, then load the next
+    //     batch (tiles with more than kHand * kBlock leavers)
     for (int q0 = tid; q0 < ntot; q0 += kHand * kBlock) {
-        int sp[kHand], cell[kHand], id[kHand];
-        R d[kHand][3], u[kHand][3];
+        if (q0 != tid) load_leavers(q0);
 #pragma unroll
         for (int h = 0; h < kHand; ++h) {
-            const int q = q0 + h * kBlock;
-            sp[h] = -1;
-            if (q < ntot) {
-                int s = 0;
-#pragma unroll
-                for (int r = 0; r + 1 < kMaxSpecies; ++r) s += (r + 1 < C.nsp && q >= sh_lend[r]) ? 1 : 0;
-                const PBuf<R> &Q = sh_q[s];
-                const int from = q + sh_loff[s];
-                cell[h] = slot_ref(Q.cell, from);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    d[h][a] = slot_ref(Q.d[a], from);
-                    u[h][a] = slot_ref(Q.u[a], from);
-                }
-                id[h] = Q.id ? slot_ref(Q.id, from) : 0;
-                sp[h] = s;
-            }
-        }
-#pragma unroll
-        for (int h = 0; h < kHand; ++h) {
-            const int s = sp[h];
+            const int s = hsp[h];
             if (s < 0) continue;
-            const int c3[3] = {cell_x(cell[h]), cell_y(cell[h]), cell_z(cell[h])};
+            const int c3[3] = {cell_x(hcell[h]), cell_y(hcell[h]), cell_z(hcell[h])};
             const int k = move_bin(g, rim, c3);         // the same bin as at staging
             const int pos = sh_base[s][k] + atomicAdd(&sh_bin[s][k], 1);
+            const bool wide = pos >= sh_tend[s][k];
             int at;
-            if (pos < sh_tend[s][k]) {
+            if (!wide) {
                 at = sh_tseg[s][k] + pos;
             } else {                                    // the target segment is full: overflow region
                 const SpeciesDev<R> &S = B.sp[s];
@@ -1448,7 +1467,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                     at = S.seg_start[dst][B.ntiles] + o;
                 }
             }
-            if (at >= 0) write_particle(sh_q[s], at, cell[h], d[h], u[h], id[h]);
+            if (at >= 0) write_particle(sh_q[s], at, wide, hcell[h], local_code(B, hcell[h]), hd[h], hu[h], hid[h]);
         }
     }
 }
@@ -1774,6 +1793,8 @@ __global__ void __launch_bounds__(kBlock) repack_scatter_kernel(const BoxDev<R> 
 {
     const Item it = items[blockIdx.x];
     const BoxDev<R> &B = boxes[it.box];
+    int o[3] = {0, 0, 0};                               // origin of the tile (tile items)
+    if (it.tile >= 0) tile_origin(B, it.tile, o);
     for (int s = 0; s < nsp; ++s) {
         const SpeciesDev<R> &S = B.sp[s];
         int first, stride;
@@ -1789,7 +1810,7 @@ __global__ void __launch_bounds__(kBlock) repack_scatter_kernel(const BoxDev<R> 
             R d[3] = {R(0), R(0), R(0)}, u[3] = {R(0), R(0), R(0)};
             if (valid) {
                 const int idx = r.slot(p);
-                cell = P.cell[idx];
+                cell = it.tile >= 0 ? local_cell(B, o, P.lc[idx]) : P.cell[idx];
                 for (int a = 0; a < 3; ++a) { d[a] = P.d[a][idx]; u[a] = P.u[a][idx]; }
                 if (P.id) id = P.id[idx];
             }
@@ -1908,7 +1929,7 @@ __global__ void __launch_bounds__(kBlock) diag_particles_kernel(const BoxDev<R> 
         double acc[6] = {0, 0, 0, 0, 0, 0};
         for (int p = first; p < r.n; p += stride) {
             const int idx = r.slot(p);
-            const int32_t cell = P.cell[idx];
+            const int32_t cell = in_tile ? local_cell(B, g.o, P.lc[idx]) : P.cell[idx];
             const int ix = cell_x(cell), iy = cell_y(cell), iz = cell_z(cell);
             R d[3] = {P.d[0][idx], P.d[1][idx], P.d[2][idx]};
             R E[3];

@@ -1531,6 +1531,16 @@ __device__ inline void after_push(const BoxDev<R> *__restrict__ boxes, const Box
     if (watch && blockIdx.x == gridDim.x - 1) overflow_watch_block(boxes, nboxes, nsp, old ^ 1, watch);
 }
 
+// Coordinates of cell p of a box with edges n0, n1 (p < n0 n1 n2 <= 2^32, so
+// 32-bit divisions are exact).
+__device__ inline void cell_coords(int64_t p, int n0, int n1, int &i, int &j, int &k)
+{
+    const uint32_t q = (uint32_t)p, r = q / (uint32_t)n0;
+    i = (int)(q - r * (uint32_t)n0);
+    k = (int)(r / (uint32_t)n1);
+    j = (int)(r - (uint32_t)k * (uint32_t)n1);
+}
+
 // b <- b - h curl e (App. A.3.2), in place.  The steps advance b inside the
 // push (its set-up writes b^{t+dt/2} of each tile's cells); this kernel makes
 // the half step of the start (h = -dt/2).
@@ -1543,7 +1553,8 @@ __global__ void __launch_bounds__(kBlock) advance_b_kernel(const BoxDev<R> *__re
     const int64_t p = (int64_t)cb.first + threadIdx.x;
     if (p >= B.nc) return;
     const int n0 = B.n[0], n1 = B.n[1], n2 = B.n[2];
-    const int i = (int)(p % n0), j = (int)((p / n0) % n1), k = (int)(p / ((int64_t)n0 * n1));
+    int i, j, k;
+    cell_coords(p, n0, n1, i, j, k);
     const int64_t sx = (i + 1 < n0) ? 1 : 1 - n0;
     const int64_t sy = (j + 1 < n1) ? n0 : (int64_t)n0 * (1 - n1);
     const int64_t sz = (k + 1 < n2) ? (int64_t)n0 * n1 : (int64_t)n0 * n1 * (1 - n2);
@@ -1579,7 +1590,8 @@ __global__ void __launch_bounds__(kBlock) advance_e_kernel(const BoxDev<R> *__re
     after_push(boxes, B, p, nsp, old, nboxes, watch);
     if (p >= B.nc) return;
     const int n0 = B.n[0], n1 = B.n[1], n2 = B.n[2];
-    const int i = (int)(p % n0), j = (int)((p / n0) % n1), k = (int)(p / ((int64_t)n0 * n1));
+    int i, j, k;
+    cell_coords(p, n0, n1, i, j, k);
     const int64_t sx = (i > 0) ? 1 : 1 - n0;
     const int64_t sy = (j > 0) ? n0 : (int64_t)n0 * (1 - n1);
     const int64_t sz = (k > 0) ? (int64_t)n0 * n1 : (int64_t)n0 * n1 * (1 - n2);
@@ -1644,7 +1656,8 @@ __global__ void __launch_bounds__(kBlock) advance_e_smoothed_kernel(const BoxDev
     after_push(boxes, B, p, nsp, old, nboxes, watch);
     if (p >= B.nc) return;
     const int n0 = B.n[0], n1 = B.n[1], n2 = B.n[2];
-    const int i = (int)(p % n0), j = (int)((p / n0) % n1), k = (int)(p / ((int64_t)n0 * n1));
+    int i, j, k;
+    cell_coords(p, n0, n1, i, j, k);
     const int64_t sx = (i > 0) ? 1 : 1 - n0;
     const int64_t sy = (j > 0) ? n0 : (int64_t)n0 * (1 - n1);
     const int64_t sz = (k > 0) ? (int64_t)n0 * n1 : (int64_t)n0 * n1 * (1 - n2);
@@ -2016,7 +2029,8 @@ __global__ void __launch_bounds__(kBlock) diag_fields_kernel(const BoxDev<R> *__
     double gmax = 0.0;
     if (p < B.nc) {
         const int n0 = B.n[0], n1 = B.n[1];
-        const int i = (int)(p % n0), j = (int)((p / n0) % n1), k = (int)(p / ((int64_t)n0 * n1));
+        int i, j, k;
+        cell_coords(p, n0, n1, i, j, k);
         for (int c = 0; c < 3; ++c) {
             const double ec = (double)B.e[c * B.nc + p];
             const double bc = (double)bt_global(B, c, i, j, k, R(0.5) * dt);

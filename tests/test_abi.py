@@ -154,8 +154,9 @@ def test_plan_sizes(P):
     d = P.pic_plan(_cfg(P, track_ids=True))
     assert 0 < a < b
     assert c > a and d > a
-    # fields (e, b: 3 FP32 each; J: 3 int64) and two particle copies of 28 B at least
-    assert a > 16 ** 3 * (24 + 24) + 2 * 2 * 32768 * 28
+    # fields (e, b: 3 FP32 each; J: 3 int64) and two particle copies of 29 B per
+    # slot at least (one-byte tile-local code, packed cell, 3 offsets, 3 momenta)
+    assert a > 16 ** 3 * (24 + 24) + 2 * 2 * 32768 * 29
 
 
 def test_plan_accepts_the_largest_box_edges(P):

@@ -352,6 +352,34 @@ def test_tiny_and_odd_boxes(dims, tile, fp64):
     s.close()
 
 
+@pytest.mark.parametrize("fp64", [False, True])
+@pytest.mark.parametrize("dims,tile", [((12, 8, 6), (8, 8, 4)), ((16, 12, 5), (8, 4, 4))])
+def test_cell_codes_at_the_largest_tiles(dims, tile, fp64):
+    # a binned particle keeps its cell as a one-byte code local to its tile;
+    # 8x8x4 tiles use all 256 codes, and these boxes end in partial tiles
+    # (x: 4 of 8 cells, z: 2 of 4; y: 4 of 4, z: 1 of 4), whose codes must
+    # give the cells back through the hand-over, the repack and the read-back
+    from paper_1308_5892_amd import pic as P
+    rng = np.random.default_rng(43)
+    n = 1500
+    s = G.sim(dims, 10.0, 16.0, [n, n], fp64=fp64, tile=tile, sort_interval=3)
+    st = G.oracle_state(dims, 10.0, 16.0)
+    e, b = G.random_fields(rng, int(np.prod(dims)), 0.02, 0.2)
+    G.start(s, st, [_random_particles(rng, dims, n) for _ in range(2)], e=e, b=b, fp64=fp64)
+    P.pic_set_timing(s.ctx, 1)                    # counts the repacks
+    s.step(7)
+    st.step(7)
+    assert P.pic_get_timing(s.ctx)["sort_launches"] >= 2
+    for sp in range(2):
+        x, u, _ = s.particles(0, sp)
+        assert len(x) == n
+        assert np.all((x >= 0) & (x < np.array(dims, float)))
+        assert G.u_rel_err(u, st.u[st.species == sp], 1e-3).max() < (1e-11 if fp64 else U32)
+    d = s.diag(0)
+    assert d["flags"] == 0 and int(d["count"].sum()) == 2 * n
+    s.close()
+
+
 @pytest.mark.parametrize("fp64,tol", [(False, 1e-5), (True, 1e-11)])
 @pytest.mark.parametrize("dims", [(2048, 2, 2), (2, 2048, 2), (2, 2, 1024)])
 def test_largest_box_edges(dims, fp64, tol):

@@ -183,14 +183,33 @@ template <typename R, int F4 = -1>
 __device__ inline void gather_global(const BoxDev<R> &B, int ix, int iy, int iz, const R d[3], R hdt,
                                      R E[3], R Bf[3])
 {
-    for (int c = 0; c < 6; ++c) {
-        R f[8], cf[8];
-        for (int q = 0; q < 8; ++q)
-            f[q] = node_value_global<R, F4>(B, c, ix + (q & 1), iy + ((q >> 1) & 1), iz + (q >> 2), hdt);
-        trilinear_coef(f, cf);
-        const R v = trilinear_eval(cf, d);
-        if (c < 3) E[c] = v;
-        else Bf[c - 3] = v;
+    if constexpr (sizeof(R) == 8) {
+        // the component loop stays rolled (each pass inlines eight node
+        // values); in the FP64 form, at three waves per SIMD, its results are
+        // selected into registers, since an array indexed by the loop counter
+        // would live in scratch there
+        R o[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+        for (int c = 0; c < 6; ++c) {
+            R f[8], cf[8];
+            for (int q = 0; q < 8; ++q)
+                f[q] = node_value_global<R, F4>(B, c, ix + (q & 1), iy + ((q >> 1) & 1), iz + (q >> 2), hdt);
+            trilinear_coef(f, cf);
+            const R v = trilinear_eval(cf, d);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) o[k] = c == k ? v : o[k];
+        }
+        E[0] = o[0]; E[1] = o[1]; E[2] = o[2];
+        Bf[0] = o[3]; Bf[1] = o[4]; Bf[2] = o[5];
+    } else {
+        for (int c = 0; c < 6; ++c) {
+            R f[8], cf[8];
+            for (int q = 0; q < 8; ++q)
+                f[q] = node_value_global<R, F4>(B, c, ix + (q & 1), iy + ((q >> 1) & 1), iz + (q >> 2), hdt);
+            trilinear_coef(f, cf);
+            const R v = trilinear_eval(cf, d);
+            if (c < 3) E[c] = v;
+            else Bf[c - 3] = v;
+        }
     }
 }
 
@@ -368,13 +387,17 @@ __device__ inline TileGeom<R> tile_geom(const BoxDev<R> &B, int T)
 // those that still have pieces left.  An entry holds the start of the next
 // piece and the end of the move (home-cell frame), the LDS index of the home
 // cell with the species sign, and the meta word of the move (move_meta).
-constexpr int kQCap = 128;
+// FP32 form: two waves' worth of entries, so that a put after a drain always
+// fits.  FP64 form: one wave's worth (a wave drains before a put that would
+// not fit), which keeps a 4x4x4 block within the LDS of three blocks per CU.
+template <typename R> struct QCap { static constexpr int value = 128; };
+template <> struct QCap<double> { static constexpr int value = 64; };
 constexpr int kWaves = kBlock / 64;
 
 template <typename R>
 __host__ __device__ inline size_t queue_bytes()
 {
-    return (size_t)kWaves * kQCap * (2 * sizeof(int32_t) + 6 * sizeof(R));
+    return (size_t)kWaves * QCap<R>::value * (2 * sizeof(int32_t) + 6 * sizeof(R));
 }
 
 // Bytes of dynamic LDS for a tile with edges (t0, t1, t2): the trilinear
@@ -773,7 +796,7 @@ __device__ inline int move_bin(const TileGeom<R> &g, const TileRim &rim, const i
 }
 
 template <typename R> struct PushWaves { static constexpr int value = 4; };
-template <> struct PushWaves<double> { static constexpr int value = 2; };
+template <> struct PushWaves<double> { static constexpr int value = 3; };
 
 template <typename R, int FIX, int WALLS, int F4>
 __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const BoxDev<R> *__restrict__ boxes,
@@ -847,7 +870,8 @@ __device__ void push_overflow(const BoxDev<R> &B, int kblk, const StepConst<R> &
 
 // FP32 form: four waves per SIMD (at most 128 VGPRs), the occupancy that
 // hides the latency of the LDS gather and of the particle loads best on
-// gfx950.  FP64 form: two (its doubled registers would spill at four).
+// gfx950.  FP64 form: three (at most 168 VGPRs; with its 64-entry queues a
+// 4x4x4 block's LDS allows three blocks per CU as well).
 template <typename R, int FIX, int WALLS, int F4>
 __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const BoxDev<R> *__restrict__ boxes,
                                                       const Item *__restrict__ items, StepConst<R> C)
@@ -1112,6 +1136,7 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
     // species sign), meta word (move_meta), start of the next piece and end
     // of the move
     const int wave = tid >> 6, lane = __lane_id();
+    constexpr int kQCap = QCap<R>::value;
     int32_t *qidx = reinterpret_cast<int32_t *>(qmem) + wave * kQCap;
     int32_t *qmeta = reinterpret_cast<int32_t *>(qmem) + (kWaves + wave) * kQCap;
     R *qval = reinterpret_cast<R *>(qmem + 2 * kWaves * kQCap * sizeof(int32_t)) + wave * 6 * kQCap;
@@ -1321,6 +1346,10 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                     atomic_add_global(&J[a * B.nc + i + (int64_t)B.n[0] * (j + (int64_t)B.n[1] * k)], q);
                 });
             }
+            if (kQCap < 128) {
+                const int cnt = (int)__popcll(__ballot(valid && inside && nb > 0));
+                while (qcount + cnt > kQCap) drain();
+            }
             put(valid && inside && nb > 0, jb | sgnbit, move_meta(1, nb, o0, o1, o2, dir), p1, x1);
             while (qcount >= 64) drain();
             if (WALLS && B.wall >= 0 && __ballot(hitw)) {
@@ -1337,6 +1366,10 @@ __global__ void __launch_bounds__(kBlock, PushWaves<R>::value) push_kernel(const
                 if (m2 < m1) { R t = m1; m1 = m2; m2 = t; int q = q1; q1 = q2; q2 = q; }
                 if (m1 < m0) { R t = m0; m0 = m1; m1 = t; int q = q0; q0 = q1; q1 = q; }
                 const int jb2 = jb + s2[0] + __mul24(JX, s2[1]) + __mul24(JXY, s2[2]);
+                if (kQCap < 128) {
+                    const int cnt = (int)__popcll(__ballot(hitw && inside));
+                    while (qcount + cnt > kQCap) drain();
+                }
                 put(hitw && inside, jb2 | sgnbit, move_meta(0, nb2, q0, q1, q2, db), P2, y1);
                 if (hitw && !inside) {
                     PIC_GLOBAL JT *J = B.J;

@@ -874,14 +874,10 @@ static int get_particles_t(pic_ctx *ctx, int box, int s, double *x, double *u, i
     HIPCHK(hipStreamSynchronize(ctx->stream));
     // a tile's ranges hold tile-local cell codes: the packed cell is the
     // tile's origin plus the code's bits
-    const int sx = D.tshift[0], sy = D.tshift[1];
     for (int t = 0; t < nt; ++t) {
-        const int r = t / D.ntile[0];
-        const int o[3] = {(t - r * D.ntile[0]) << sx, (r % D.ntile[1]) << sy, (r / D.ntile[1]) << D.tshift[2]};
-        auto decode = [&](int64_t k) {
-            const int c = code[k];
-            cell[k] = pack_cell(o[0] + (c & ((1 << sx) - 1)), o[1] + ((c >> sx) & ((1 << sy) - 1)), o[2] + (c >> (sx + sy)));
-        };
+        int o[3];
+        tile_origin(D, t, o);
+        auto decode = [&](int64_t k) { cell[k] = local_cell(D, o, code[k]); };
         for (int k = 0; k < na[t]; ++k) decode(start[t] + k);
         const int nbv = std::max(0, std::min(nb[t], cap[t] - bs[t]));
         for (int k = 0; k < nbv; ++k) decode(start[t] + bs[t] + k);

@@ -159,7 +159,7 @@ __device__ inline int local_code(const BoxDev<R> &B, int32_t c)
 }
 
 template <typename R>
-__device__ inline int32_t local_cell(const BoxDev<R> &B, const int o[3], int code)
+__host__ __device__ inline int32_t local_cell(const BoxDev<R> &B, const int o[3], int code)
 {
     const int sx = B.tshift[0], sy = B.tshift[1];
     return pack_cell(o[0] + (code & ((1 << sx) - 1)), o[1] + ((code >> sx) & ((1 << sy) - 1)), o[2] + (code >> (sx + sy)));
@@ -167,7 +167,7 @@ __device__ inline int32_t local_cell(const BoxDev<R> &B, const int o[3], int cod
 
 // Origin cell of tile T.
 template <typename R>
-__device__ inline void tile_origin(const BoxDev<R> &B, int T, int o[3])
+__host__ __device__ inline void tile_origin(const BoxDev<R> &B, int T, int o[3])
 {
     const int r = T / B.ntile[0];
     o[0] = (T - r * B.ntile[0]) << B.tshift[0];
